@@ -1,0 +1,187 @@
+"""Benchmark: D3Q19 LB-IMB-DEM throughput (MLUPS) on one MI355X.
+
+One step = the whole hot path: particle footprint / solid fraction, fused pull
+stream + LBGK/IMB collision, per-particle hydrodynamic force and torque, DEM
+cell list + contacts, particle integration.  The headline workload is the
+D3Q19 suspension 192x756x192 (periodic x/z, walls y, 8317 spheres R = 4 at
+solid fraction 0.08, density ratio 1000, tau 0.6, gravity along -y), in FP64;
+the FP32-shifted and FP16-storage variants are timed on the same input.
+
+Prints ONE JSON line.  value = FP64 MLUPS (lattice nodes x steps / wall s).
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "D3Q19 LB-IMB MLUPS (FP64 vs FP32-shifted) and % of HBM roofline"
+BYTES_PER_VALUE = {"fp64": 8, "fp32s": 4, "fp16s": 2}
+DTYPE = {"fp64": "f64", "fp32s": "f32", "fp16s": "f16-storage/f32"}
+
+
+def kernel_source_sha():
+    with open(os.path.join(ROOT, "paper_1011_2613_amd", "csrc", "lb_kernels.hip"), "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def measured_traffic(storage, workload):
+    """HBM bytes per launch of the lattice kernel from the committed rocprofv3
+    counter runs, if they were taken on the current kernel source."""
+    path = os.path.join(ROOT, "profiles", "lb_kernel_traffic.json")
+    try:
+        with open(path) as f:
+            d = json.load(f)
+    except (OSError, ValueError):
+        return None
+    rec = d.get("%s_%s" % (workload, storage))
+    if not rec or rec.get("kernel_source_sha") != kernel_source_sha():
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def run_variant(binding, inputs, w, parts, storage, steps, warmup):
+    import torch
+    sim = binding.Simulation(w.dim, w.shape, w.tau, storage=storage, wall_y=w.wall_y,
+                             fluid_force=w.fluid_force, particle_accel=w.particle_accel,
+                             samples=w.samples, kn=w.kn, restitution=w.restitution,
+                             max_particles=w.count)
+    sim.set_particles(*parts)
+    sim.step(warmup)
+    sim.set_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.step(steps)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    phases = sim.get_timing()
+    sim.set_timing(False)
+    wall = t1 - t0
+    mlups = w.nodes * steps / wall / 1e6
+    lat_ms, lat_n = phases["lattice"]
+    avg_ms = lat_ms / max(lat_n, 1)
+    Q = 9 if w.dim == 2 else 19
+    bpn = 2 * Q * BYTES_PER_VALUE[storage]
+    achieved = bpn * w.nodes / (avg_ms * 1e-3) / 1e9
+    traffic = measured_traffic(storage, w.name)
+    sim.close()
+    del sim
+    torch.cuda.empty_cache()
+    return {
+        "mlups": mlups, "ms_per_step": wall / steps * 1e3, "wall_s": wall,
+        "lattice_kernel_ms": avg_ms, "bytes_per_node": bpn,
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": traffic},
+        "phase_ms_per_step": {k: round(v[0] / max(v[1], 1), 4) for k, v in phases.items()},
+    }
+
+
+def cpu_baseline(w, parts):
+    """The FP64 CPU oracle, single thread, one full step of the same workload."""
+    from oracle import oracle as O
+    orc = O.OracleSim(w.dim, w.shape, w.tau, wall_y=w.wall_y, fluid_force=w.fluid_force,
+                      particle_accel=w.particle_accel, samples=w.samples, kn=w.kn,
+                      restitution=w.restitution)
+    orc.set_particles(*parts)
+    steps = 1
+    t0 = time.perf_counter()
+    orc.step(steps)
+    dt = time.perf_counter() - t0
+    orc.close()
+    return {"value": round(w.nodes * steps / dt / 1e6, 3), "unit": "MLUPS", "cores": 1,
+            "kind": "oracle",
+            "sample": "%d step of the full %s lattice (%d nodes, %d particles), %.1f s"
+                      % (steps, w.name, w.nodes, w.count, dt)}
+
+
+def copy_calibration(gib=2.0, reps=10):
+    """A plain device-to-device copy of known size: the reference for scaling
+    the HBM byte counters and the achievable copy bandwidth."""
+    import torch
+    n = int(gib * 2 ** 30) // 8
+    src = torch.ones(n, dtype=torch.float64, device="cuda:0")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / reps
+    moved = 2 * n * 8
+    print(json.dumps({"copy_bytes_read_per_launch": n * 8, "copy_bytes_written_per_launch": n * 8,
+                      "copy_GBps": round(moved / dt / 1e9, 1), "launches": reps + 1}), flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=300)
+    ap.add_argument("--warmup", type=int, default=30)
+    ap.add_argument("--workload", default="C3")
+    ap.add_argument("--variants", default="fp64,fp32s,fp16s")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 2 GiB device copy (counter calibration)")
+    args = ap.parse_args()
+    if args.copy_calibration:
+        copy_calibration()
+        return
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(--gpus %d requested)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1011_2613_amd import binding, inputs
+    binding.load()
+    w = inputs.workload(args.workload)
+    parts = w.particles()
+    variants = [v for v in args.variants.split(",") if v]
+    if "fp64" not in variants:
+        variants = ["fp64"] + variants
+    res = {}
+    for v in variants:
+        res[v] = run_variant(binding, inputs, w, parts, v, args.steps, args.warmup)
+        print("# %s: %.1f MLUPS, lattice kernel %.3f ms, %.1f GB/s"
+              % (v, res[v]["mlups"], res[v]["lattice_kernel_ms"], res[v]["roofline"]["achieved"]),
+              file=sys.stderr, flush=True)
+    base = res["fp64"]
+    out = {
+        "metric": METRIC,
+        "value": round(base["mlups"], 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(base["ms_per_step"], 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": DTYPE["fp64"],
+        "data": "synthetic (seeded random sphere placement, fluid at rest)",
+        "config": {"workload": "%s: D3Q19 %dx%dx%d, walls y, %d spheres R=%g, tau %g, density ratio %g"
+                   % (w.name, *w.shape, w.count, w.radius, w.tau, w.rho_ratio),
+                   "nodes": w.nodes, "particles": w.count, "storage": "fp64"},
+        "roofline": base["roofline"],
+        "phase_ms_per_step": base["phase_ms_per_step"],
+        "variants": {v: {"value": round(r["mlups"], 1), "unit": "MLUPS", "dtype": DTYPE[v],
+                         "ms_per_step": round(r["ms_per_step"], 4),
+                         "roofline": r["roofline"], "phase_ms_per_step": r["phase_ms_per_step"],
+                         "speedup_vs_fp64": round(r["mlups"] / base["mlups"], 3)}
+                     for v, r in res.items() if v != "fp64"},
+        "device": torch.cuda.get_device_name(0),
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(w, parts)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

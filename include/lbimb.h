@@ -1,0 +1,175 @@
+/*
+ * lbimb.h -- C ABI of the MI355X LB-IMB-DEM library (liblbimb.so).
+ *
+ * The library advances a lattice-Boltzmann fluid (D2Q9 or D3Q19, LBGK)
+ * coupled to rigid particles by the Noble-Torczynski immersed moving boundary
+ * and moved by a frictionless soft-sphere DEM, following Xiong et al.,
+ * "Large-Scale DNS of Gas-Solid Flow on Mole-8.5" ("Numerical scheme",
+ * Eqs. 1-5).  Every step runs on one GPU in hand-written HIP kernels.
+ *
+ * Conventions for every call
+ *   - Return value: LBM_OK (0) or a negative LBM_E_* code.  No C++ exception
+ *     crosses this boundary.  lbm_last_error() gives a message for the last
+ *     failing call on a context.
+ *   - Units are lattice units (lattice spacing h = 1, time step dt = 1).
+ *   - Lattice fields are stored with x fastest: node n = x + nx*(y + ny*z).
+ *     Populations are [Q][N], velocities [D][N], densities [N].
+ *   - Particle arrays are [n][3] doubles (2D: z components are zero on output
+ *     and ignored on input; the angular velocity uses component z only).
+ *   - ptr_kind: LBM_HOST (0) means a host pointer; the call finishes the copy
+ *     before returning.  LBM_DEVICE (1) means a device pointer on the
+ *     context's GPU; the call is asynchronous on the context's stream.
+ *   - Ownership: the caller owns the workspace and all input and output
+ *     buffers; the library copies inputs and keeps no caller pointer except
+ *     the workspace, which must stay allocated until lbm_destroy().
+ *   - A context is bound to one HIP stream and is not thread-safe.
+ */
+#ifndef LBIMB_H
+#define LBIMB_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---------------------------------------------------------------- codes */
+enum {
+    LBM_OK = 0,
+    LBM_E_INVALID = -1,          /* bad argument or configuration */
+    LBM_E_NOMEM = -2,            /* workspace too small */
+    LBM_E_HIP = -3,              /* a HIP runtime call failed */
+    LBM_E_NONFINITE = -4,        /* a non-finite value was found in the state */
+    LBM_E_SLOT_OVERFLOW = -5,    /* more than LBM_MAX_OWNERS particles cover one node */
+    LBM_E_STATE = -6,            /* call out of order (e.g. step before particles) */
+    LBM_E_IO = -7,               /* save/load file error */
+    LBM_E_CELL_OVERFLOW = -8,    /* a DEM cell holds more than its capacity */
+    LBM_E_CONTACT_OVERFLOW = -9  /* a particle has more than LBM_MAX_CONTACTS contacts */
+};
+
+enum { LBM_D2Q9 = 0, LBM_D3Q19 = 1 };
+
+/* Storage of the populations.  FP64 stores f_i; FP32_SHIFTED stores
+ * g_i = f_i - w_i in binary32 and computes in binary32; FP16_STORE stores
+ * g_i / w_i in binary16 and computes in binary32.  Particle forces, torques
+ * and motion are binary64 in every mode. */
+enum { LBM_FP64 = 0, LBM_FP32_SHIFTED = 1, LBM_FP16_STORE = 2 };
+
+enum { LBM_HOST = 0, LBM_DEVICE = 1 };
+
+#define LBM_MAX_OWNERS 4      /* particles that may cover one node */
+#define LBM_MAX_CONTACTS 32   /* contacts per particle per step */
+#define LBM_MAX_PARTICLES 4194303
+
+typedef struct lbm_config {
+    int lattice;            /* LBM_D2Q9 or LBM_D3Q19 */
+    int storage;            /* LBM_FP64, LBM_FP32_SHIFTED or LBM_FP16_STORE */
+    int nx, ny, nz;         /* lattice size; nz = 1 for D2Q9 */
+    int wall_y;             /* 0: periodic in y; 1: halfway bounce-back walls at
+                               y = -1/2 and y = ny - 1/2.  x and z are periodic. */
+    double tau;             /* BGK relaxation time, > 1/2 (Eq. 1) */
+    double fluid_force[3];  /* body force per unit mass on the fluid; enters as
+                               F_i = 3 w_i rho (c_i . g) (Eq. 1, term F_i) */
+    double particle_accel[3]; /* acceleration of every free particle (gravity
+                                 including buoyancy) */
+    int eps_samples;        /* S: sub-cell sample points per axis for the solid
+                               fraction eps (S^D samples per node, 1..8) */
+    double kn;              /* DEM normal stiffness (Eq. 4) */
+    double restitution;     /* DEM restitution coefficient e, 0 < e <= 1 (Eq. 5) */
+    int max_particles;      /* capacity reserved in the workspace */
+} lbm_config;
+
+typedef struct lbm_ctx lbm_ctx;
+
+/* Device bytes the caller must provide for `cfg` (any alignment >= 256). */
+int lbm_workspace_bytes(const lbm_config *cfg, size_t *bytes);
+
+/* Validates `cfg` (tau > 1/2, sizes, samples), lays out the state inside
+ * `workspace` (device memory of at least lbm_workspace_bytes), binds the
+ * context to `hip_stream` (a hipStream_t; NULL means the null stream) and
+ * sets the fluid to rest, f = f^eq(1, 0).  Errors: LBM_E_INVALID,
+ * LBM_E_NOMEM, LBM_E_HIP. */
+int lbm_create(const lbm_config *cfg, void *workspace, size_t ws_bytes,
+               void *hip_stream, lbm_ctx **out);
+
+void lbm_destroy(lbm_ctx *ctx);
+
+/* Replaces the particle set.  pos/vel/omega [n][3], radius/rho_s [n],
+ * fixed [n] (1: the particle never moves; its force and torque are still
+ * reported).  Mass is rho_s pi R^2 (disc of unit depth) or rho_s 4/3 pi R^3,
+ * moment of inertia m R^2 / 2 or 2 m R^2 / 5.  `fixed` may be NULL.  Host
+ * pointers only for this call (ptr_kind must be LBM_HOST).  Errors:
+ * LBM_E_INVALID (n > max_particles, radius <= 0, a particle wider than the
+ * periodic box, a centre outside the box, two particles overlapping by more
+ * than half the smaller radius). */
+int lbm_set_particles(lbm_ctx *ctx, int64_t n, const double *pos, const double *vel,
+                      const double *omega, const double *radius, const double *rho_s,
+                      const uint8_t *fixed, int ptr_kind);
+
+/* Sets the pre-collision populations f(x, t), [Q][N] binary64, converting
+ * them to the storage format. */
+int lbm_set_distributions(lbm_ctx *ctx, const double *f, int ptr_kind);
+
+/* Gets the pre-collision populations f(x, t), [Q][N] binary64 (for shifted
+ * storage: w_i + g_i, or w_i + w_i h_i). */
+int lbm_get_distributions(lbm_ctx *ctx, double *f, int ptr_kind);
+
+/* Advances `nsteps` time steps.  One step: particle footprint and solid
+ * fraction; fused pull streaming + LBGK/IMB collision (Eqs. 1-2); hydrodynamic
+ * force and torque per particle (Eq. 3); DEM contacts (Eqs. 4-5); symplectic
+ * Euler update of the particles.  Returns after the work is queued and the
+ * health flags of the call are read back (which synchronises the stream).
+ * Errors: LBM_E_SLOT_OVERFLOW, LBM_E_CELL_OVERFLOW, LBM_E_CONTACT_OVERFLOW,
+ * LBM_E_HIP, LBM_E_STATE. */
+int lbm_step(lbm_ctx *ctx, int64_t nsteps);
+
+/* Hydrodynamic force and torque on each particle from the last completed
+ * step, [n][3] binary64 (Eq. 3, sign: force exerted by the fluid on the
+ * particle). */
+int lbm_get_forces(lbm_ctx *ctx, double *F, double *T, int ptr_kind);
+
+/* DEM contact force on each particle from the last completed step, [n][3]. */
+int lbm_get_contact_forces(lbm_ctx *ctx, double *Fc, int ptr_kind);
+
+/* Particle state at the current time, [n][3] each. */
+int lbm_get_particles(lbm_ctx *ctx, double *pos, double *vel, double *omega, int ptr_kind);
+
+/* Moments of the pre-collision populations f(x, t): rho [N] and
+ * u [D][N] = sum_i f_i c_i / rho, binary64 in every storage mode. */
+int lbm_get_macro(lbm_ctx *ctx, double *rho, double *u, int ptr_kind);
+
+/* IMB momentum exchange q_n = beta_n sum_i Omega^S_i c_i of the last step,
+ * [D][N] binary64; zero where no particle covers the node. */
+int lbm_get_q(lbm_ctx *ctx, double *q, int ptr_kind);
+
+/* Number of completed time steps. */
+int64_t lbm_time(const lbm_ctx *ctx);
+
+/* Number of particles currently set (after lbm_set_particles or lbm_load). */
+int64_t lbm_particle_count(const lbm_ctx *ctx);
+
+/* Per-phase kernel timing.  While enabled, lbm_step launches the step kernels
+ * one by one (no graph) with HIP events around each phase on the context's
+ * stream; lbm_get_timing synchronises and returns the summed milliseconds and
+ * the number of launches of each phase since timing was enabled.
+ * Phases: 0 footprint (clear + paint), 1 lattice (stream-collide-IMB),
+ * 2 hydrodynamic force, 3 cell list, 4 DEM contacts, 5 integration. */
+#define LBM_NPHASES 6
+int lbm_set_timing(lbm_ctx *ctx, int enable);
+int lbm_get_timing(lbm_ctx *ctx, double *ms, int64_t *launches);
+
+/* Writes / reads the full state (populations in storage format, particles,
+ * forces, time) to / from a file.  The file records the configuration; a
+ * mismatching file gives LBM_E_INVALID. */
+int lbm_save(lbm_ctx *ctx, const char *path);
+int lbm_load(lbm_ctx *ctx, const char *path);
+
+const char *lbm_error_string(int code);
+const char *lbm_last_error(const lbm_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LBIMB_H */

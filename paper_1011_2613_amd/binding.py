@@ -1,0 +1,280 @@
+"""Thin ctypes binding of liblbimb.so (C ABI in include/lbimb.h).
+
+Argument marshalling only: every step of the method runs in the library's HIP
+kernels.  PyTorch supplies the device workspace and the HIP stream.  The
+binding fails loudly when the native library has not been built; there is no
+fallback implementation.
+"""
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liblbimb.so")
+
+LBM_OK = 0
+LBM_D2Q9, LBM_D3Q19 = 0, 1
+LBM_FP64, LBM_FP32_SHIFTED, LBM_FP16_STORE = 0, 1, 2
+LBM_HOST, LBM_DEVICE = 0, 1
+LBM_NPHASES = 6
+PHASES = ("footprint", "lattice", "force", "cells", "dem", "integrate")
+STORAGE = {"fp64": LBM_FP64, "fp32s": LBM_FP32_SHIFTED, "fp16s": LBM_FP16_STORE}
+ERRORS = {-1: "LBM_E_INVALID", -2: "LBM_E_NOMEM", -3: "LBM_E_HIP", -4: "LBM_E_NONFINITE",
+          -5: "LBM_E_SLOT_OVERFLOW", -6: "LBM_E_STATE", -7: "LBM_E_IO",
+          -8: "LBM_E_CELL_OVERFLOW", -9: "LBM_E_CONTACT_OVERFLOW"}
+
+
+class lbm_config(C.Structure):
+    _fields_ = [("lattice", C.c_int), ("storage", C.c_int), ("nx", C.c_int), ("ny", C.c_int),
+                ("nz", C.c_int), ("wall_y", C.c_int), ("tau", C.c_double),
+                ("fluid_force", C.c_double * 3), ("particle_accel", C.c_double * 3),
+                ("eps_samples", C.c_int), ("kn", C.c_double), ("restitution", C.c_double),
+                ("max_particles", C.c_int)]
+
+
+class LbmError(RuntimeError):
+    def __init__(self, code, msg=""):
+        self.code = code
+        super().__init__("%s (%d): %s" % (ERRORS.get(code, "error"), code, msg))
+
+
+_lib = None
+_SYMBOLS = ("lbm_workspace_bytes", "lbm_create", "lbm_destroy", "lbm_set_particles",
+            "lbm_set_distributions", "lbm_get_distributions", "lbm_step", "lbm_get_forces",
+            "lbm_get_contact_forces", "lbm_get_particles", "lbm_get_macro", "lbm_get_q",
+            "lbm_time", "lbm_particle_count", "lbm_set_timing", "lbm_get_timing", "lbm_save", "lbm_load",
+            "lbm_error_string", "lbm_last_error")
+
+
+def load():
+    """Load liblbimb.so; raises if it has not been built (no fallback)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError("liblbimb.so is not built: run `python -m paper_1011_2613_amd.build` "
+                           "(or __graft_entry__.build()) first")
+    # PyTorch-ROCm carries its own HIP runtime (soname libamdhip64.so.7).  Load
+    # it first so that the library binds to that same runtime: one runtime per
+    # process, so torch's streams and device memory are valid handles here.
+    import torch  # noqa: F401
+    L = C.CDLL(LIB_PATH)
+    vp, dp, i64 = C.c_void_p, C.POINTER(C.c_double), C.c_int64
+    L.lbm_workspace_bytes.argtypes = [C.POINTER(lbm_config), C.POINTER(C.c_size_t)]
+    L.lbm_create.argtypes = [C.POINTER(lbm_config), vp, C.c_size_t, vp, C.POINTER(vp)]
+    L.lbm_destroy.argtypes = [vp]
+    L.lbm_destroy.restype = None
+    L.lbm_set_particles.argtypes = [vp, i64, vp, vp, vp, vp, vp, vp, C.c_int]
+    L.lbm_set_distributions.argtypes = [vp, vp, C.c_int]
+    L.lbm_get_distributions.argtypes = [vp, vp, C.c_int]
+    L.lbm_step.argtypes = [vp, i64]
+    L.lbm_get_forces.argtypes = [vp, vp, vp, C.c_int]
+    L.lbm_get_contact_forces.argtypes = [vp, vp, C.c_int]
+    L.lbm_get_particles.argtypes = [vp, vp, vp, vp, C.c_int]
+    L.lbm_get_macro.argtypes = [vp, vp, vp, C.c_int]
+    L.lbm_get_q.argtypes = [vp, vp, C.c_int]
+    L.lbm_time.argtypes = [vp]
+    L.lbm_time.restype = i64
+    L.lbm_particle_count.argtypes = [vp]
+    L.lbm_particle_count.restype = i64
+    L.lbm_set_timing.argtypes = [vp, C.c_int]
+    L.lbm_get_timing.argtypes = [vp, dp, C.POINTER(i64)]
+    L.lbm_save.argtypes = [vp, C.c_char_p]
+    L.lbm_load.argtypes = [vp, C.c_char_p]
+    L.lbm_error_string.argtypes = [C.c_int]
+    L.lbm_error_string.restype = C.c_char_p
+    L.lbm_last_error.argtypes = [vp]
+    L.lbm_last_error.restype = C.c_char_p
+    for name in _SYMBOLS:
+        if name not in ("lbm_destroy", "lbm_time", "lbm_particle_count", "lbm_error_string",
+                        "lbm_last_error"):
+            getattr(L, name).restype = C.c_int
+    _lib = L
+    return L
+
+
+def exported_symbols():
+    return _SYMBOLS
+
+
+def _ptr(a):
+    if a is None:
+        return None
+    if hasattr(a, "data_ptr"):
+        return C.c_void_p(a.data_ptr())
+    return C.c_void_p(a.ctypes.data)
+
+
+def _f64(a, shape):
+    return np.ascontiguousarray(np.asarray(a, dtype=np.float64).reshape(shape))
+
+
+class Simulation:
+    """One LB-IMB-DEM context on one GPU (see include/lbimb.h for semantics).
+
+    shape is (nx, ny) for D2Q9 and (nx, ny, nz) for D3Q19.  Host-side getters
+    return numpy arrays shaped like the lattice ([.., nz, ny, nx]).
+    """
+
+    def __init__(self, dim, shape, tau, storage="fp64", wall_y=False, fluid_force=(0, 0, 0),
+                 particle_accel=(0, 0, 0), samples=4, kn=0.0, restitution=0.9,
+                 max_particles=1, device="cuda:0"):
+        import torch
+        self._torch = torch
+        L = load()
+        self.dim = dim
+        self.Q = 9 if dim == 2 else 19
+        nx, ny = int(shape[0]), int(shape[1])
+        nz = int(shape[2]) if dim == 3 else 1
+        self.nx, self.ny, self.nz = nx, ny, nz
+        self.N = nx * ny * nz
+        cfg = lbm_config()
+        cfg.lattice = LBM_D2Q9 if dim == 2 else LBM_D3Q19
+        cfg.storage = STORAGE[storage] if isinstance(storage, str) else int(storage)
+        cfg.nx, cfg.ny, cfg.nz = nx, ny, nz
+        cfg.wall_y = int(bool(wall_y))
+        cfg.tau = float(tau)
+        ff = list(fluid_force) + [0.0] * (3 - len(fluid_force))
+        pa = list(particle_accel) + [0.0] * (3 - len(particle_accel))
+        for a in range(3):
+            cfg.fluid_force[a] = float(ff[a])
+            cfg.particle_accel[a] = float(pa[a])
+        cfg.eps_samples = int(samples)
+        cfg.kn = float(kn)
+        cfg.restitution = float(restitution)
+        cfg.max_particles = int(max_particles)
+        self.cfg = cfg
+        nbytes = C.c_size_t(0)
+        self._check(L.lbm_workspace_bytes(C.byref(cfg), C.byref(nbytes)))
+        self.device = torch.device(device)
+        self.workspace = torch.empty(int(nbytes.value) + 256, dtype=torch.uint8, device=self.device)
+        base = self.workspace.data_ptr()
+        aligned = (base + 255) // 256 * 256
+        self.stream = torch.cuda.Stream(device=self.device)
+        h = C.c_void_p()
+        self._ctx = None
+        self._check(L.lbm_create(C.byref(cfg), C.c_void_p(aligned), C.c_size_t(int(nbytes.value)),
+                                 C.c_void_p(self.stream.cuda_stream), C.byref(h)))
+        self._ctx = h
+        self.np_ = 0
+
+    # ----------------------------------------------------------- plumbing
+    def _check(self, rc):
+        if rc != LBM_OK:
+            msg = ""
+            msg = load().lbm_last_error(getattr(self, "_ctx", None)).decode()
+            raise LbmError(rc, msg)
+
+    def close(self):
+        if getattr(self, "_ctx", None):
+            load().lbm_destroy(self._ctx)
+            self._ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def field_shape(self):
+        return (self.nz, self.ny, self.nx) if self.dim == 3 else (self.ny, self.nx)
+
+    def synchronize(self):
+        self.stream.synchronize()
+
+    # ----------------------------------------------------------------- ABI
+    def set_particles(self, pos, vel=None, omega=None, radius=None, rho_s=None, fixed=None):
+        pos = _f64(pos, (-1, 3))
+        n = pos.shape[0]
+        vel = _f64(np.zeros((n, 3)) if vel is None else vel, (n, 3))
+        omega = _f64(np.zeros((n, 3)) if omega is None else omega, (n, 3))
+        radius = _f64(radius, (n,))
+        rho_s = _f64(rho_s, (n,))
+        fx = None if fixed is None else np.ascontiguousarray(np.asarray(fixed, dtype=np.uint8).reshape(n))
+        self._check(load().lbm_set_particles(self._ctx, n, _ptr(pos), _ptr(vel), _ptr(omega),
+                                             _ptr(radius), _ptr(rho_s), _ptr(fx), LBM_HOST))
+        self.np_ = n
+
+    def set_f(self, f):
+        f = _f64(f, (self.Q, self.N))
+        self._check(load().lbm_set_distributions(self._ctx, _ptr(f), LBM_HOST))
+
+    def get_f(self):
+        f = np.empty((self.Q,) + self.field_shape)
+        self._check(load().lbm_get_distributions(self._ctx, _ptr(f), LBM_HOST))
+        return f
+
+    def step(self, n=1):
+        self._check(load().lbm_step(self._ctx, int(n)))
+
+    @property
+    def t(self):
+        return int(load().lbm_time(self._ctx))
+
+    def macro(self):
+        rho = np.empty(self.field_shape)
+        u = np.empty((self.dim,) + self.field_shape)
+        self._check(load().lbm_get_macro(self._ctx, _ptr(rho), _ptr(u), LBM_HOST))
+        return rho, u
+
+    def macro_device(self):
+        """(rho, u) as device tensors, computed on the library's stream."""
+        torch = self._torch
+        rho = torch.empty(self.field_shape, dtype=torch.float64, device=self.device)
+        u = torch.empty((self.dim,) + self.field_shape, dtype=torch.float64, device=self.device)
+        self._check(load().lbm_get_macro(self._ctx, _ptr(rho), _ptr(u), LBM_DEVICE))
+        torch.cuda.current_stream(self.device).wait_stream(self.stream)
+        return rho, u
+
+    def q(self):
+        q = np.empty((self.dim,) + self.field_shape)
+        self._check(load().lbm_get_q(self._ctx, _ptr(q), LBM_HOST))
+        return q
+
+    def forces(self):
+        n = max(self.np_, 1)
+        F = np.zeros((n, 3)); T = np.zeros((n, 3))
+        self._check(load().lbm_get_forces(self._ctx, _ptr(F), _ptr(T), LBM_HOST))
+        return F[: self.np_], T[: self.np_]
+
+    def contact_forces(self):
+        Fc = np.zeros((max(self.np_, 1), 3))
+        self._check(load().lbm_get_contact_forces(self._ctx, _ptr(Fc), LBM_HOST))
+        return Fc[: self.np_]
+
+    def particles(self):
+        n = max(self.np_, 1)
+        x = np.zeros((n, 3)); v = np.zeros((n, 3)); w = np.zeros((n, 3))
+        self._check(load().lbm_get_particles(self._ctx, _ptr(x), _ptr(v), _ptr(w), LBM_HOST))
+        return x[: self.np_], v[: self.np_], w[: self.np_]
+
+    def set_timing(self, on):
+        self._check(load().lbm_set_timing(self._ctx, int(bool(on))))
+
+    def get_timing(self):
+        ms = (C.c_double * LBM_NPHASES)()
+        n = (C.c_int64 * LBM_NPHASES)()
+        self._check(load().lbm_get_timing(self._ctx, ms, n))
+        return {PHASES[k]: (ms[k], n[k]) for k in range(LBM_NPHASES)}
+
+    def save(self, path):
+        self._check(load().lbm_save(self._ctx, str(path).encode()))
+
+    def load_state(self, path):
+        self._check(load().lbm_load(self._ctx, str(path).encode()))
+        self.np_ = int(load().lbm_particle_count(self._ctx))
+
+
+def simulation_for(workload, storage="fp64", device="cuda:0", with_particles=True):
+    """A Simulation set up for an inputs.Workload (particles placed, fluid at rest)."""
+    w = workload
+    sim = Simulation(w.dim, w.shape, w.tau, storage=storage, wall_y=w.wall_y,
+                     fluid_force=w.fluid_force, particle_accel=w.particle_accel,
+                     samples=w.samples, kn=w.kn, restitution=w.restitution,
+                     max_particles=max(w.count, 1), device=device)
+    if with_particles and w.count > 0:
+        pos, vel, om, rad, rho, fixed = w.particles()
+        sim.set_particles(pos, vel, om, rad, rho, fixed)
+    return sim

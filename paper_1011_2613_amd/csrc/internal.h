@@ -1,0 +1,139 @@
+// internal.h -- device-side data layout, lattice traits and launcher
+// declarations shared by the HIP translation units of liblbimb.so.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace lbimb {
+
+// ---------------------------------------------------------------- lattices
+// D2Q9 and D3Q19 velocity sets (the paper's "Numerical scheme").  Ordering:
+// rest first, then axis directions, then diagonals; opposite directions are
+// adjacent so that opp() is a table lookup.  The weight class k selects
+// w = {4/9, 1/9, 1/36} (D2Q9) or {1/3, 1/18, 1/36} (D3Q19).
+struct D2Q9 {
+    static constexpr int D = 2, Q = 9;
+    static constexpr int cx[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
+    static constexpr int cy[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+    static constexpr int cz[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    static constexpr int opp[9] = {0, 3, 4, 1, 2, 7, 8, 5, 6};
+    static constexpr int wc[9] = {0, 1, 1, 1, 1, 2, 2, 2, 2};
+    static constexpr double w[3] = {4.0 / 9.0, 1.0 / 9.0, 1.0 / 36.0};
+    static constexpr float invw[3] = {2.25f, 9.0f, 36.0f};
+};
+
+struct D3Q19 {
+    static constexpr int D = 3, Q = 19;
+    static constexpr int cx[19] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0};
+    static constexpr int cy[19] = {0, 0, 0, 1, -1, 0, 0, 1, -1, -1, 1, 0, 0, 0, 0, 1, -1, 1, -1};
+    static constexpr int cz[19] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, -1, 1, 1, -1, -1, 1};
+    static constexpr int opp[19] = {0, 2, 1, 4, 3, 6, 5, 8, 7, 10, 9, 12, 11, 14, 13, 16, 15, 18, 17};
+    static constexpr int wc[19] = {0, 1, 1, 1, 1, 1, 1, 2, 2, 2, 2, 2, 2, 2, 2, 2, 2, 2, 2};
+    static constexpr double w[3] = {1.0 / 3.0, 1.0 / 18.0, 1.0 / 36.0};
+    static constexpr float invw[3] = {3.0f, 18.0f, 36.0f};
+};
+
+enum : uint32_t {
+    FLAG_SLOT_OVERFLOW = 1u,
+    FLAG_CELL_OVERFLOW = 2u,
+    FLAG_CONTACT_OVERFLOW = 4u,
+    FLAG_NONFINITE = 8u,
+};
+
+constexpr int MAX_OWNERS = 4;
+constexpr int MAX_CONTACTS = 32;
+constexpr int CELL_CAP = 16;
+constexpr int SLOT_COUNT_BITS = 10;  // count of sub-samples (<= 512) in the low bits
+
+// Particle state, structure of arrays, binary64.  Vectors are [3][P].
+struct Particles {
+    double *x, *v, *w;     // position, velocity, angular velocity
+    double *R, *m, *I;     // radius, mass, moment of inertia
+    uint8_t *fixed;
+    double *Fh, *Th, *Fc;  // hydrodynamic force/torque, contact force
+    int *bb;               // [3][P] lower corner of the painted bounding box
+    int np;
+};
+
+// Lattice geometry shared by every kernel.
+struct Geom {
+    int nx, ny, nz;
+    int wall_y;
+    int64_t N;
+    double Lx, Ly, Lz;     // box lengths as doubles
+};
+
+// Arguments of the fused stream-collide-IMB kernel.
+struct LBArgs {
+    const void *A;         // post-collision populations of the previous step
+    void *B;               // post-collision populations of this step
+    const uint8_t *nown;   // owners per node
+    const uint32_t *slots; // [MAX_OWNERS][N] (pid << 10 | count)
+    const double *beta_tab;   // beta(eps) for count 0..Smax
+    const double *arel_tab;   // (1 - beta) / tau for count 0..Smax
+    double *q;             // [D][N] IMB momentum exchange
+    const double *px, *pv, *pw;  // particle SoA
+    int np;
+    Geom g;
+    int Smax;
+    double arel0;          // 1 / tau
+    double cg[19];         // c_i . g_fluid per direction
+    float cgf[19];
+    float arel0f;
+    float tauf;
+    uint32_t *flags;
+};
+
+struct FootArgs {
+    Particles P;
+    Geom g;
+    uint8_t *nown;
+    uint32_t *slots;
+    int S;
+    uint32_t *flags;
+};
+
+struct ForceArgs {
+    Particles P;
+    Geom g;
+    const uint8_t *nown;
+    const uint32_t *slots;
+    const double *q;
+    int S;
+    int D;
+};
+
+struct CellArgs {
+    Particles P;
+    Geom g;
+    int ncx, ncy, ncz;
+    int *cell_count;
+    int *cell_ids;         // [ncell][CELL_CAP]
+    uint32_t *flags;
+    int D;
+    double kn, ce;
+    double ap[3];
+};
+
+// launchers (lb_kernels.hip)
+hipError_t launch_lb(int lattice, int storage, const LBArgs &a, hipStream_t s);
+hipError_t launch_get_f(int lattice, int storage, const Geom &g, const void *A, double *f,
+                        hipStream_t s);
+hipError_t launch_set_f(int lattice, int storage, const Geom &g, const double *f, void *A,
+                        hipStream_t s);
+hipError_t launch_macro(int lattice, int storage, const Geom &g, const void *A, double *rho,
+                        double *u, hipStream_t s);
+hipError_t launch_fill_u32(uint32_t *p, uint32_t value, int64_t count, hipStream_t s);
+hipError_t launch_fill_u64(uint64_t *p, uint64_t value, int64_t count, hipStream_t s);
+
+// launchers (particle_kernels.hip)
+hipError_t launch_foot_clear(const FootArgs &a, hipStream_t s);
+hipError_t launch_foot_paint(const FootArgs &a, int D, hipStream_t s);
+hipError_t launch_foot_bbox(const FootArgs &a, int D, hipStream_t s);
+hipError_t launch_force(const ForceArgs &a, hipStream_t s);
+hipError_t launch_cells(const CellArgs &a, hipStream_t s);
+hipError_t launch_dem(const CellArgs &a, hipStream_t s);
+hipError_t launch_integrate(const CellArgs &a, hipStream_t s);
+
+}  // namespace lbimb

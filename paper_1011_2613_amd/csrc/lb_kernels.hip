@@ -1,0 +1,488 @@
+// lb_kernels.hip -- fused pull-streaming + LBGK collision with the
+// Noble-Torczynski immersed-moving-boundary terms, for gfx950.
+//
+// One thread updates one node.  The state array A holds the post-collision
+// populations of the previous step; the kernel gathers f_i(x, t) = A_i(x - c_i)
+// (halfway bounce-back: A_opp(i)(x) when x - c_i lies beyond a wall), applies
+// Eq. 1 with the weight beta of Eq. 2 and the solid operator Omega^S, and
+// writes the new post-collision populations to B at x.  Reads of the shifted
+// neighbours are unaligned by one element but every population is read once
+// and written once: 2 Q s bytes per node of HBM traffic.  Structure of arrays
+// f[i][z][y][x] keeps each wavefront's 64 consecutive x on contiguous lines.
+//
+// Covered nodes (a particle's sub-cell samples fall in the cell) also read
+// their owner records and particle velocities, and write q_n, the momentum
+// the IMB term hands to the fluid, which the force kernel sums per particle
+// (Eq. 3).
+//
+// FP64 evaluation order is fixed: every sum runs over the directions in index
+// order, every product and quotient is taken exactly as in the paper's
+// formulas with no fused multiply-add (the library is built with
+// -ffp-contract=off), so the result is reproducible bit for bit.
+#include "internal.h"
+
+namespace lbimb {
+
+// ------------------------------------------------------------ storage
+template <int ST> struct Store;
+template <> struct Store<0> { using T = double; };
+template <> struct Store<1> { using T = float; };
+template <> struct Store<2> { using T = _Float16; };
+
+__device__ __forceinline__ double disp_periodic(double d, double L) {
+    if (d > 0.5 * L) d = d - L;
+    else if (d < -0.5 * L) d = d + L;
+    return d;
+}
+
+// Displacement node coordinate - particle coordinate along axis a.
+__device__ __forceinline__ double node_disp(const Geom &g, int axis, int coord, double xp) {
+    double d = (double)coord - xp;
+    if (axis == 0) return disp_periodic(d, g.Lx);
+    if (axis == 1) return g.wall_y ? d : disp_periodic(d, g.Ly);
+    return disp_periodic(d, g.Lz);
+}
+
+// Sorts up to 4 owner records ascending (missing entries are 0xffffffff).
+__device__ __forceinline__ void sort4(uint32_t &a, uint32_t &b, uint32_t &c, uint32_t &d) {
+#define LBIMB_CSWAP(p, q) { uint32_t lo_ = min(p, q), hi_ = max(p, q); p = lo_; q = hi_; }
+    LBIMB_CSWAP(a, b); LBIMB_CSWAP(c, d); LBIMB_CSWAP(a, c); LBIMB_CSWAP(b, d); LBIMB_CSWAP(b, c);
+#undef LBIMB_CSWAP
+}
+
+// Solid velocity V_S at node (x,y,z): count-weighted mean of the owners'
+// rigid-body velocities v_p + omega_p x (x_n - x_p), owners in ascending id.
+// Returns the total sub-sample count.
+template <class L>
+__device__ __forceinline__ int solid_velocity(const LBArgs &a, int64_t n, int nown, int x, int y,
+                                              int z, double V[3]) {
+    const int64_t N = a.g.N;
+    uint32_t r[4] = {0xffffffffu, 0xffffffffu, 0xffffffffu, 0xffffffffu};
+    const int k = nown < MAX_OWNERS ? nown : MAX_OWNERS;
+    for (int j = 0; j < k; j++) r[j] = a.slots[(int64_t)j * N + n];
+    sort4(r[0], r[1], r[2], r[3]);
+    int total = 0;
+    double num[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+    for (int j = 0; j < MAX_OWNERS; j++) {
+        if (j < k) {
+            const int p = (int)(r[j] >> SLOT_COUNT_BITS);
+            const int cnt = (int)(r[j] & ((1u << SLOT_COUNT_BITS) - 1u));
+            total += cnt;
+            const int P = a.np;
+            const double rx = node_disp(a.g, 0, x, a.px[p]);
+            const double ry = node_disp(a.g, 1, y, a.px[P + p]);
+            double vr[3];
+            if (L::D == 3) {
+                const double rz = node_disp(a.g, 2, z, a.px[2 * P + p]);
+                const double wx = a.pw[p], wy = a.pw[P + p], wz = a.pw[2 * P + p];
+                vr[0] = a.pv[p] + (wy * rz - wz * ry);
+                vr[1] = a.pv[P + p] + (wz * rx - wx * rz);
+                vr[2] = a.pv[2 * P + p] + (wx * ry - wy * rx);
+            } else {
+                const double wz = a.pw[2 * P + p];
+                vr[0] = a.pv[p] - wz * ry;
+                vr[1] = a.pv[P + p] + wz * rx;
+                vr[2] = 0.0;
+            }
+            const double c = (double)cnt;
+#pragma unroll
+            for (int d = 0; d < L::D; d++) num[d] = num[d] + c * vr[d];
+        }
+    }
+    const double den = (double)total;
+#pragma unroll
+    for (int d = 0; d < 3; d++) V[d] = d < L::D ? num[d] / den : 0.0;
+    return total;
+}
+
+// c_i . u with the zero components of c_i dropped (exact for c in {-1,0,1}).
+template <class L, class R>
+__device__ __forceinline__ R cdot(int i, R ux, R uy, R uz) {
+    R s = R(0);
+    bool first = true;
+    if (L::cx[i] != 0) { s = L::cx[i] > 0 ? ux : -ux; first = false; }
+    if (L::cy[i] != 0) {
+        if (first) { s = L::cy[i] > 0 ? uy : -uy; first = false; }
+        else s = L::cy[i] > 0 ? s + uy : s - uy;
+    }
+    if (L::D == 3 && L::cz[i] != 0) {
+        if (first) { s = L::cz[i] > 0 ? uz : -uz; first = false; }
+        else s = L::cz[i] > 0 ? s + uz : s - uz;
+    }
+    return s;
+}
+
+// Sum over directions of c_ia * v_i, index order, zero terms dropped.
+template <class L, int AX, class R>
+__device__ __forceinline__ R cmoment(const R (&v)[L::Q]) {
+    R s = R(0);
+#pragma unroll
+    for (int i = 0; i < L::Q; i++) {
+        const int c = AX == 0 ? L::cx[i] : (AX == 1 ? L::cy[i] : L::cz[i]);
+        if (c > 0) s = s + v[i];
+        else if (c < 0) s = s - v[i];
+    }
+    return s;
+}
+
+// ------------------------------------------------------------- pull gather
+template <class L, class T>
+__device__ __forceinline__ void gather(const T *__restrict__ A, const Geom &g, int x, int y, int z,
+                                       int64_t n, T (&f)[L::Q]) {
+    const int nx = g.nx, ny = g.ny, nz = g.nz;
+    const int64_t N = g.N;
+    const int xm = x == 0 ? nx - 1 : x - 1, xp = x == nx - 1 ? 0 : x + 1;
+    int ym = y - 1, yp = y + 1;
+    bool lo = false, hi = false;
+    if (g.wall_y) {
+        lo = (y == 0);
+        hi = (y == ny - 1);
+    } else {
+        if (ym < 0) ym = ny - 1;
+        if (yp >= ny) yp = 0;
+    }
+    const int zm = z == 0 ? nz - 1 : z - 1, zp = z == nz - 1 ? 0 : z + 1;
+#pragma unroll
+    for (int i = 0; i < L::Q; i++) {
+        const int sx = L::cx[i] == 0 ? x : (L::cx[i] > 0 ? xm : xp);
+        const int sy = L::cy[i] == 0 ? y : (L::cy[i] > 0 ? ym : yp);
+        const int sz = L::cz[i] == 0 ? z : (L::cz[i] > 0 ? zm : zp);
+        const bool bb = (L::cy[i] > 0 && lo) || (L::cy[i] < 0 && hi);
+        const int64_t src = bb ? (int64_t)L::opp[i] * N + n
+                               : (int64_t)i * N + (int64_t)sx + (int64_t)nx * ((int64_t)sy + (int64_t)ny * sz);
+        f[i] = A[src];
+    }
+}
+
+// ------------------------------------------------------ FP64 collision
+template <class L>
+__device__ __forceinline__ void collide_f64(const LBArgs &a, int64_t n, int x, int y, int z,
+                                            double (&f)[L::Q], int nown) {
+    double rho = f[0];
+#pragma unroll
+    for (int i = 1; i < L::Q; i++) rho = rho + f[i];
+    const double jx = cmoment<L, 0>(f), jy = cmoment<L, 1>(f);
+    const double jz = L::D == 3 ? cmoment<L, 2>(f) : 0.0;
+    const double ux = jx / rho, uy = jy / rho, uz = L::D == 3 ? jz / rho : 0.0;
+    double usq = ux * ux + uy * uy;
+    if (L::D == 3) usq = usq + uz * uz;
+    const double t15 = 1.5 * usq;
+    const double wr[3] = {L::w[0] * rho, L::w[1] * rho, L::w[2] * rho};
+    const double w3r[3] = {3.0 * L::w[0] * rho, 3.0 * L::w[1] * rho, 3.0 * L::w[2] * rho};
+
+    double feq[L::Q];
+#pragma unroll
+    for (int i = 0; i < L::Q; i++) {
+        if (i == 0) {
+            feq[i] = wr[0] * (1.0 - t15);
+        } else {
+            const double cu = cdot<L>(i, ux, uy, uz);
+            feq[i] = wr[L::wc[i]] * (1.0 + 3.0 * cu + 4.5 * cu * cu - t15);
+        }
+    }
+
+    double out[L::Q];
+    if (nown == 0) {
+        const double ar = a.arel0;
+#pragma unroll
+        for (int i = 0; i < L::Q; i++)
+            out[i] = f[i] - ar * (f[i] - feq[i]) + w3r[L::wc[i]] * a.cg[i];
+    } else {
+        if (nown > MAX_OWNERS) atomicOr(a.flags, FLAG_SLOT_OVERFLOW);
+        double V[3];
+        const int total = solid_velocity<L>(a, n, nown, x, y, z, V);
+        const int cc = total < a.Smax ? total : a.Smax;
+        const double beta = a.beta_tab[cc];
+        const double ar = a.arel_tab[cc];
+        double VV = V[0] * V[0] + V[1] * V[1];
+        if (L::D == 3) VV = VV + V[2] * V[2];
+        const double v15 = 1.5 * VV;
+        double Om[L::Q];
+#pragma unroll
+        for (int i = 0; i < L::Q; i++) {
+            double feqV;
+            if (i == 0) {
+                feqV = wr[0] * (1.0 - v15);
+            } else {
+                const double cV = cdot<L>(i, V[0], V[1], V[2]);
+                feqV = wr[L::wc[i]] * (1.0 + 3.0 * cV + 4.5 * cV * cV - v15);
+            }
+            const int o = L::opp[i];
+            Om[i] = (f[o] - f[i]) + (feqV - feq[o]);
+        }
+#pragma unroll
+        for (int i = 0; i < L::Q; i++)
+            out[i] = f[i] - ar * (f[i] - feq[i]) + beta * Om[i] + w3r[L::wc[i]] * a.cg[i];
+        const int64_t N = a.g.N;
+        a.q[n] = beta * cmoment<L, 0>(Om);
+        a.q[N + n] = beta * cmoment<L, 1>(Om);
+        if (L::D == 3) a.q[2 * N + n] = beta * cmoment<L, 2>(Om);
+    }
+    double *B = (double *)a.B;
+#pragma unroll
+    for (int i = 0; i < L::Q; i++) __builtin_nontemporal_store(out[i], &B[(int64_t)i * a.g.N + n]);
+}
+
+// ------------------------------------------- shifted storage, FP32 compute
+// g_i = f_i - w_i (rho_0 = 1):  drho = sum g, rho = 1 + drho, u = sum g c / rho,
+// g^eq_i = w_i (drho + rho (3 cu + 4.5 cu^2 - 1.5 u^2)); the solid operator
+// keeps its exact form because the w_i terms cancel:
+// Omega_i = (g_-i - g_i) + w_i rho [(3 cV + 4.5 cV^2 - 1.5 V^2) - (-3 cu + 4.5 cu^2 - 1.5 u^2)].
+template <class L, int ST>
+__device__ __forceinline__ void collide_shifted(const LBArgs &a, int64_t n, int x, int y, int z,
+                                                float (&gg)[L::Q], int nown) {
+    float drho = gg[0];
+#pragma unroll
+    for (int i = 1; i < L::Q; i++) drho = drho + gg[i];
+    const float rho = 1.0f + drho;
+    const float jx = cmoment<L, 0>(gg), jy = cmoment<L, 1>(gg);
+    const float jz = L::D == 3 ? cmoment<L, 2>(gg) : 0.0f;
+    const float ux = jx / rho, uy = jy / rho, uz = L::D == 3 ? jz / rho : 0.0f;
+    float usq = ux * ux + uy * uy;
+    if (L::D == 3) usq = usq + uz * uz;
+    const float t15 = 1.5f * usq;
+    const float wf[3] = {(float)L::w[0], (float)L::w[1], (float)L::w[2]};
+
+    float geq[L::Q], cus[L::Q];
+#pragma unroll
+    for (int i = 0; i < L::Q; i++) {
+        const float cu = i == 0 ? 0.0f : cdot<L>(i, ux, uy, uz);
+        cus[i] = cu;
+        geq[i] = wf[L::wc[i]] * (drho + rho * (3.0f * cu + 4.5f * cu * cu - t15));
+    }
+    float out[L::Q];
+    if (nown == 0) {
+        const float ar = a.arel0f;
+#pragma unroll
+        for (int i = 0; i < L::Q; i++)
+            out[i] = gg[i] - ar * (gg[i] - geq[i]) + (3.0f * wf[L::wc[i]] * rho) * a.cgf[i];
+    } else {
+        if (nown > MAX_OWNERS) atomicOr(a.flags, FLAG_SLOT_OVERFLOW);
+        double Vd[3];
+        const int total = solid_velocity<L>(a, n, nown, x, y, z, Vd);
+        const int cc = total < a.Smax ? total : a.Smax;
+        const float beta = (float)a.beta_tab[cc];
+        const float ar = (float)a.arel_tab[cc];
+        const float V0 = (float)Vd[0], V1 = (float)Vd[1], V2 = (float)Vd[2];
+        float VV = V0 * V0 + V1 * V1;
+        if (L::D == 3) VV = VV + V2 * V2;
+        const float v15 = 1.5f * VV;
+        float Om[L::Q];
+#pragma unroll
+        for (int i = 0; i < L::Q; i++) {
+            const float cV = i == 0 ? 0.0f : cdot<L>(i, V0, V1, V2);
+            const float cu = cus[i];
+            const float pV = 3.0f * cV + 4.5f * cV * cV - v15;
+            const float pu = -3.0f * cu + 4.5f * cu * cu - t15;
+            Om[i] = (gg[L::opp[i]] - gg[i]) + (wf[L::wc[i]] * rho) * (pV - pu);
+        }
+#pragma unroll
+        for (int i = 0; i < L::Q; i++)
+            out[i] = gg[i] - ar * (gg[i] - geq[i]) + beta * Om[i] + (3.0f * wf[L::wc[i]] * rho) * a.cgf[i];
+        const int64_t N = a.g.N;
+        a.q[n] = (double)(beta * cmoment<L, 0>(Om));
+        a.q[N + n] = (double)(beta * cmoment<L, 1>(Om));
+        if (L::D == 3) a.q[2 * N + n] = (double)(beta * cmoment<L, 2>(Om));
+    }
+    using T = typename Store<ST>::T;
+    T *B = (T *)a.B;
+#pragma unroll
+    for (int i = 0; i < L::Q; i++) {
+        T v;
+        if (ST == 1) v = (T)out[i];
+        else v = (T)(out[i] * L::invw[L::wc[i]]);
+        __builtin_nontemporal_store(v, &B[(int64_t)i * a.g.N + n]);
+    }
+}
+
+template <class L, int ST>
+__global__ __launch_bounds__(256) void k_lb(LBArgs a) {
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= a.g.nx) return;
+    const int y = blockIdx.y, z = blockIdx.z;
+    const int64_t n = (int64_t)x + (int64_t)a.g.nx * ((int64_t)y + (int64_t)a.g.ny * z);
+    using T = typename Store<ST>::T;
+    T f[L::Q];
+    gather<L, T>((const T *)a.A, a.g, x, y, z, n, f);
+    const int nown = a.nown[n];
+    if (ST == 0) {
+        double fd[L::Q];
+#pragma unroll
+        for (int i = 0; i < L::Q; i++) fd[i] = (double)f[i];
+        collide_f64<L>(a, n, x, y, z, fd, nown);
+    } else {
+        float gg[L::Q];
+        const float wf[3] = {(float)L::w[0], (float)L::w[1], (float)L::w[2]};
+#pragma unroll
+        for (int i = 0; i < L::Q; i++)
+            gg[i] = ST == 1 ? (float)f[i] : wf[L::wc[i]] * (float)f[i];
+        collide_shifted<L, ST>(a, n, x, y, z, gg, nown);
+    }
+}
+
+// ---------------------------------------------- state conversion kernels
+// Decoded population f_i = w_i + g_i in binary64.
+template <class L, int ST>
+__device__ __forceinline__ double decode(int i, typename Store<ST>::T v) {
+    if (ST == 0) return (double)v;
+    const float wf = (float)L::w[L::wc[i]];
+    const float gv = ST == 1 ? (float)v : wf * (float)v;
+    return L::w[L::wc[i]] + (double)gv;
+}
+
+template <class L, int ST>
+__device__ __forceinline__ typename Store<ST>::T encode(int i, double fv) {
+    using T = typename Store<ST>::T;
+    if (ST == 0) return (T)fv;
+    const float gv = (float)(fv - L::w[L::wc[i]]);
+    if (ST == 1) return (T)gv;
+    return (T)(gv * L::invw[L::wc[i]]);
+}
+
+template <class L, int ST>
+__global__ void k_get_f(Geom g, const void *A, double *f) {
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= g.nx) return;
+    const int y = blockIdx.y, z = blockIdx.z;
+    const int64_t n = (int64_t)x + (int64_t)g.nx * ((int64_t)y + (int64_t)g.ny * z);
+    using T = typename Store<ST>::T;
+    T v[L::Q];
+    gather<L, T>((const T *)A, g, x, y, z, n, v);
+#pragma unroll
+    for (int i = 0; i < L::Q; i++) f[(int64_t)i * g.N + n] = decode<L, ST>(i, v[i]);
+}
+
+template <class L, int ST>
+__global__ void k_macro(Geom g, const void *A, double *rho, double *u) {
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= g.nx) return;
+    const int y = blockIdx.y, z = blockIdx.z;
+    const int64_t n = (int64_t)x + (int64_t)g.nx * ((int64_t)y + (int64_t)g.ny * z);
+    using T = typename Store<ST>::T;
+    T v[L::Q];
+    gather<L, T>((const T *)A, g, x, y, z, n, v);
+    double fd[L::Q];
+#pragma unroll
+    for (int i = 0; i < L::Q; i++) fd[i] = decode<L, ST>(i, v[i]);
+    double r = fd[0];
+#pragma unroll
+    for (int i = 1; i < L::Q; i++) r = r + fd[i];
+    rho[n] = r;
+    u[n] = cmoment<L, 0>(fd) / r;
+    u[g.N + n] = cmoment<L, 1>(fd) / r;
+    if (L::D == 3) u[2 * g.N + n] = cmoment<L, 2>(fd) / r;
+}
+
+// Inverse of the pull streaming: A_j(x) = f_j(x + c_j), or f_opp(j)(x) when
+// x + c_j lies beyond a wall.
+template <class L, int ST>
+__global__ void k_set_f(Geom g, const double *f, void *Av) {
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= g.nx) return;
+    const int y = blockIdx.y, z = blockIdx.z;
+    const int64_t n = (int64_t)x + (int64_t)g.nx * ((int64_t)y + (int64_t)g.ny * z);
+    using T = typename Store<ST>::T;
+    T *A = (T *)Av;
+#pragma unroll
+    for (int j = 0; j < L::Q; j++) {
+        int tx = x + L::cx[j], ty = y + L::cy[j], tz = z + L::cz[j];
+        tx = tx < 0 ? tx + g.nx : (tx >= g.nx ? tx - g.nx : tx);
+        tz = tz < 0 ? tz + g.nz : (tz >= g.nz ? tz - g.nz : tz);
+        bool beyond = false;
+        if (g.wall_y) beyond = ty < 0 || ty >= g.ny;
+        else ty = ty < 0 ? ty + g.ny : (ty >= g.ny ? ty - g.ny : ty);
+        double val;
+        if (beyond) val = f[(int64_t)L::opp[j] * g.N + n];
+        else val = f[(int64_t)j * g.N + (int64_t)tx + (int64_t)g.nx * ((int64_t)ty + (int64_t)g.ny * tz)];
+        A[(int64_t)j * g.N + n] = encode<L, ST>(j, val);
+    }
+}
+
+__global__ void k_fill_u32(uint32_t *p, uint32_t value, int64_t count) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t k = i; k < count; k += stride) p[k] = value;
+}
+
+__global__ void k_fill_u64(uint64_t *p, uint64_t value, int64_t count) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t k = i; k < count; k += stride) p[k] = value;
+}
+
+// ---------------------------------------------------------------- launchers
+static dim3 lattice_grid(const Geom &g, int &block) {
+    block = g.nx >= 256 ? 256 : ((g.nx + 63) / 64) * 64;
+    return dim3((unsigned)((g.nx + block - 1) / block), (unsigned)g.ny, (unsigned)g.nz);
+}
+
+template <class L, int ST>
+static hipError_t lb_dispatch(const LBArgs &a, hipStream_t s) {
+    int block;
+    dim3 grid = lattice_grid(a.g, block);
+    hipLaunchKernelGGL((k_lb<L, ST>), grid, dim3(block), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_lb(int lattice, int storage, const LBArgs &a, hipStream_t s) {
+    if (lattice == 0) {
+        if (storage == 0) return lb_dispatch<D2Q9, 0>(a, s);
+        if (storage == 1) return lb_dispatch<D2Q9, 1>(a, s);
+        return lb_dispatch<D2Q9, 2>(a, s);
+    }
+    if (storage == 0) return lb_dispatch<D3Q19, 0>(a, s);
+    if (storage == 1) return lb_dispatch<D3Q19, 1>(a, s);
+    return lb_dispatch<D3Q19, 2>(a, s);
+}
+
+#define LBIMB_DISPATCH(KERNEL, ...)                                                          \
+    do {                                                                                     \
+        int block_;                                                                          \
+        dim3 grid_ = lattice_grid(g, block_);                                                \
+        if (lattice == 0) {                                                                  \
+            if (storage == 0) hipLaunchKernelGGL((KERNEL<D2Q9, 0>), grid_, dim3(block_), 0, s, __VA_ARGS__); \
+            else if (storage == 1) hipLaunchKernelGGL((KERNEL<D2Q9, 1>), grid_, dim3(block_), 0, s, __VA_ARGS__); \
+            else hipLaunchKernelGGL((KERNEL<D2Q9, 2>), grid_, dim3(block_), 0, s, __VA_ARGS__); \
+        } else {                                                                             \
+            if (storage == 0) hipLaunchKernelGGL((KERNEL<D3Q19, 0>), grid_, dim3(block_), 0, s, __VA_ARGS__); \
+            else if (storage == 1) hipLaunchKernelGGL((KERNEL<D3Q19, 1>), grid_, dim3(block_), 0, s, __VA_ARGS__); \
+            else hipLaunchKernelGGL((KERNEL<D3Q19, 2>), grid_, dim3(block_), 0, s, __VA_ARGS__); \
+        }                                                                                    \
+    } while (0)
+
+hipError_t launch_get_f(int lattice, int storage, const Geom &g, const void *A, double *f,
+                        hipStream_t s) {
+    LBIMB_DISPATCH(k_get_f, g, A, f);
+    return hipGetLastError();
+}
+
+hipError_t launch_set_f(int lattice, int storage, const Geom &g, const double *f, void *A,
+                        hipStream_t s) {
+    LBIMB_DISPATCH(k_set_f, g, f, A);
+    return hipGetLastError();
+}
+
+hipError_t launch_macro(int lattice, int storage, const Geom &g, const void *A, double *rho,
+                        double *u, hipStream_t s) {
+    LBIMB_DISPATCH(k_macro, g, A, rho, u);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_u32(uint32_t *p, uint32_t value, int64_t count, hipStream_t s) {
+    if (count <= 0) return hipSuccess;
+    int64_t blocks = (count + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)blocks), dim3(256), 0, s, p, value, count);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_u64(uint64_t *p, uint64_t value, int64_t count, hipStream_t s) {
+    if (count <= 0) return hipSuccess;
+    int64_t blocks = (count + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL(k_fill_u64, dim3((unsigned)blocks), dim3(256), 0, s, p, value, count);
+    return hipGetLastError();
+}
+
+}  // namespace lbimb

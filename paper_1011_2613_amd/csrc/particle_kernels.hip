@@ -1,0 +1,475 @@
+// particle_kernels.hip -- particle side of the LB-IMB-DEM step on gfx950:
+// footprint / solid fraction, hydrodynamic force and torque sums (Eq. 3),
+// DEM cell list, contact forces (Eqs. 4-5) and time integration.
+//
+// All particle arithmetic is binary64 in every storage mode.  Sums whose
+// order differs from a sequential loop (the per-particle force reduction) use
+// error-free TwoSum accumulation (Ogita, Rump & Oishi 2005) so the rounded
+// result does not depend on the reduction tree.
+#include "internal.h"
+
+namespace lbimb {
+
+__device__ __forceinline__ double pdisp(double d, double L) {
+    if (d > 0.5 * L) d = d - L;
+    else if (d < -0.5 * L) d = d + L;
+    return d;
+}
+
+__device__ __forceinline__ double ndisp(const Geom &g, int axis, int coord, double xp) {
+    double d = (double)coord - xp;
+    if (axis == 0) return pdisp(d, g.Lx);
+    if (axis == 1) return g.wall_y ? d : pdisp(d, g.Ly);
+    return pdisp(d, g.Lz);
+}
+
+// Wrap an unwrapped node coordinate; -1 beyond a wall.
+__device__ __forceinline__ int wrapc(const Geom &g, int axis, int c) {
+    const int n = axis == 0 ? g.nx : (axis == 1 ? g.ny : g.nz);
+    if (axis == 1 && g.wall_y) return (c < 0 || c >= n) ? -1 : c;
+    c %= n;
+    return c < 0 ? c + n : c;
+}
+
+// Bounding box of nodes whose cell may hold samples of the particle:
+// ceil(x - R - 1/2) .. floor(x + R + 1/2) per axis.
+__device__ __forceinline__ void bbox(const Particles &P, int p, int D, int lo[3], int hi[3]) {
+    const double r = P.R[p];
+    for (int a = 0; a < 3; a++) {
+        if (a >= D) { lo[a] = hi[a] = 0; continue; }
+        const double c = P.x[a * P.np + p];
+        lo[a] = (int)ceil(c - r - 0.5);
+        hi[a] = (int)floor(c + r + 0.5);
+    }
+}
+
+__global__ void k_foot_bbox(FootArgs a, int D) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= a.P.np) return;
+    int lo[3], hi[3];
+    bbox(a.P, p, D, lo, hi);
+    for (int d = 0; d < 3; d++) {
+        a.P.bb[d * a.P.np + p] = lo[d];
+        a.P.bb[(3 + d) * a.P.np + p] = hi[d];
+    }
+}
+
+// Zero the owner counts of every node painted in the previous step.
+__global__ __launch_bounds__(256) void k_foot_clear(FootArgs a) {
+    const int p = blockIdx.x;
+    const int P = a.P.np;
+    int lo[3], ext[3];
+    for (int d = 0; d < 3; d++) {
+        lo[d] = a.P.bb[d * P + p];
+        ext[d] = a.P.bb[(3 + d) * P + p] - lo[d] + 1;
+    }
+    const int total = ext[0] * ext[1] * ext[2];
+    for (int k = threadIdx.x; k < total; k += blockDim.x) {
+        const int cx = lo[0] + k % ext[0];
+        const int cy = lo[1] + (k / ext[0]) % ext[1];
+        const int cz = lo[2] + k / (ext[0] * ext[1]);
+        const int ix = wrapc(a.g, 0, cx), iy = wrapc(a.g, 1, cy), iz = wrapc(a.g, 2, cz);
+        if (iy < 0) continue;
+        a.nown[(int64_t)ix + (int64_t)a.g.nx * ((int64_t)iy + (int64_t)a.g.ny * iz)] = 0;
+    }
+}
+
+// Paint the particle's footprint: count of sub-cell samples inside the
+// particle per node (sample offsets (k + 1/2)/S - 1/2 per axis, inside test
+// dx^2 + dy^2 (+ dz^2) <= R^2 evaluated left to right), then claim an owner
+// slot on every covered node.  The squared offsets are separable, so each
+// node needs S^D additions; nodes whose nearest sample is outside or whose
+// farthest sample is inside are decided from per-axis extremes, exactly,
+// because rounded addition is monotone.
+__global__ __launch_bounds__(256) void k_foot_paint(FootArgs a, int D) {
+    const int p = blockIdx.x;
+    const int P = a.P.np;
+    const int S = a.S;
+    int lo[3], hi[3];
+    bbox(a.P, p, D, lo, hi);
+    if (threadIdx.x == 0)
+        for (int d = 0; d < 3; d++) {
+            a.P.bb[d * P + p] = lo[d];
+            a.P.bb[(3 + d) * P + p] = hi[d];
+        }
+    const int ext0 = hi[0] - lo[0] + 1, ext1 = hi[1] - lo[1] + 1, ext2 = hi[2] - lo[2] + 1;
+    const int total = ext0 * ext1 * ext2;
+    const double r = a.P.R[p];
+    const double R2 = r * r;
+    const double xp0 = a.P.x[p], xp1 = a.P.x[P + p], xp2 = D == 3 ? a.P.x[2 * P + p] : 0.0;
+    const int64_t N = a.g.N;
+    for (int k = threadIdx.x; k < total; k += blockDim.x) {
+        const int cx = lo[0] + k % ext0;
+        const int cy = lo[1] + (k / ext0) % ext1;
+        const int cz = lo[2] + k / (ext0 * ext1);
+        const int ix = wrapc(a.g, 0, cx), iy = wrapc(a.g, 1, cy);
+        const int iz = D == 3 ? wrapc(a.g, 2, cz) : 0;
+        if (iy < 0) continue;
+        const double d0 = ndisp(a.g, 0, ix, xp0);
+        const double d1 = ndisp(a.g, 1, iy, xp1);
+        const double d2 = D == 3 ? ndisp(a.g, 2, iz, xp2) : 0.0;
+        double sx[8], sy[8], sz[8];
+        double mnx = 1e300, mxx = -1.0, mny = 1e300, mxy = -1.0, mnz = 1e300, mxz = -1.0;
+        for (int s = 0; s < S; s++) {
+            const double off = ((double)s + 0.5) / (double)S - 0.5;
+            const double ex = d0 + off, ey = d1 + off;
+            sx[s] = ex * ex;
+            sy[s] = ey * ey;
+            mnx = fmin(mnx, sx[s]); mxx = fmax(mxx, sx[s]);
+            mny = fmin(mny, sy[s]); mxy = fmax(mxy, sy[s]);
+            if (D == 3) {
+                const double ez = d2 + off;
+                sz[s] = ez * ez;
+                mnz = fmin(mnz, sz[s]); mxz = fmax(mxz, sz[s]);
+            }
+        }
+        int count;
+        if (D == 2) {
+            if (mnx + mny > R2) count = 0;
+            else if (mxx + mxy <= R2) count = S * S;
+            else {
+                count = 0;
+                for (int ky = 0; ky < S; ky++)
+                    for (int kx = 0; kx < S; kx++) count += (sx[kx] + sy[ky] <= R2) ? 1 : 0;
+            }
+        } else {
+            if (mnx + mny + mnz > R2) count = 0;
+            else if (mxx + mxy + mxz <= R2) count = S * S * S;
+            else {
+                count = 0;
+                for (int kz = 0; kz < S; kz++)
+                    for (int ky = 0; ky < S; ky++) {
+                        const double sxy0 = sy[ky];
+                        for (int kx = 0; kx < S; kx++) count += (sx[kx] + sxy0 + sz[kz] <= R2) ? 1 : 0;
+                    }
+            }
+        }
+        if (count == 0) continue;
+        const int64_t n = (int64_t)ix + (int64_t)a.g.nx * ((int64_t)iy + (int64_t)a.g.ny * iz);
+        uint32_t *word = (uint32_t *)(a.nown + (n & ~(int64_t)3));
+        const int sh = 8 * (int)(n & 3);
+        const uint32_t old = atomicAdd(word, 1u << sh);
+        const int slot = (int)((old >> sh) & 0xffu);
+        if (slot < MAX_OWNERS)
+            a.slots[(int64_t)slot * N + n] = ((uint32_t)p << SLOT_COUNT_BITS) | (uint32_t)count;
+        else
+            atomicOr(a.flags, FLAG_SLOT_OVERFLOW);
+    }
+}
+
+// ------------------------------------------------- hydrodynamic force, Eq. 3
+struct Acc {
+    double s, c;
+};
+
+__device__ __forceinline__ void acc_add(Acc &A, double p) {
+    const double x = A.s + p;
+    const double bb = x - A.s;
+    const double e = (A.s - (x - bb)) + (p - bb);
+    A.s = x;
+    A.c = A.c + e;
+}
+
+__device__ __forceinline__ void acc_merge(Acc &A, const Acc &B) {
+    const double x = A.s + B.s;
+    const double bb = x - A.s;
+    const double e = (A.s - (x - bb)) + (B.s - bb);
+    A.s = x;
+    A.c = (A.c + B.c) + e;
+}
+
+__device__ __forceinline__ double shfl_xor_d(double v, int m) {
+    return __shfl_xor(v, m, 64);
+}
+
+// One wavefront per particle: lanes walk the particle's bounding box, add
+// s_pn q_n and r_pn x (s_pn q_n) into TwoSum accumulators, then the 64 lanes
+// merge their accumulators with butterfly shuffles.  F_p = -sum, T_p = -sum.
+__global__ __launch_bounds__(256) void k_force(ForceArgs a) {
+    const int lane = threadIdx.x & 63;
+    const int p = blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
+    const int P = a.P.np;
+    if (p >= P) return;
+    const int D = a.D;
+    int lo[3], ext[3];
+    for (int d = 0; d < 3; d++) {
+        lo[d] = a.P.bb[d * P + p];
+        ext[d] = a.P.bb[(3 + d) * P + p] - lo[d] + 1;
+    }
+    const int total = ext[0] * ext[1] * ext[2];
+    const double xp0 = a.P.x[p], xp1 = a.P.x[P + p], xp2 = D == 3 ? a.P.x[2 * P + p] : 0.0;
+    const int64_t N = a.g.N;
+    Acc F[3] = {{0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}};
+    Acc T[3] = {{0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}};
+    for (int k = lane; k < total; k += 64) {
+        const int cx = lo[0] + k % ext[0];
+        const int cy = lo[1] + (k / ext[0]) % ext[1];
+        const int cz = lo[2] + k / (ext[0] * ext[1]);
+        const int ix = wrapc(a.g, 0, cx), iy = wrapc(a.g, 1, cy);
+        const int iz = D == 3 ? wrapc(a.g, 2, cz) : 0;
+        if (iy < 0) continue;
+        const int64_t n = (int64_t)ix + (int64_t)a.g.nx * ((int64_t)iy + (int64_t)a.g.ny * iz);
+        const int no = a.nown[n];
+        if (no == 0) continue;
+        const int kk = no < MAX_OWNERS ? no : MAX_OWNERS;
+        int cnt = 0, tot = 0;
+        for (int j = 0; j < kk; j++) {
+            const uint32_t r = a.slots[(int64_t)j * N + n];
+            const int c = (int)(r & ((1u << SLOT_COUNT_BITS) - 1u));
+            tot += c;
+            if ((int)(r >> SLOT_COUNT_BITS) == p) cnt = c;
+        }
+        if (cnt == 0) continue;
+        const double sh = (double)cnt / (double)tot;
+        double t[3];
+        t[0] = sh * a.q[n];
+        t[1] = sh * a.q[N + n];
+        t[2] = D == 3 ? sh * a.q[2 * N + n] : 0.0;
+        const double rx = ndisp(a.g, 0, ix, xp0);
+        const double ry = ndisp(a.g, 1, iy, xp1);
+        acc_add(F[0], t[0]);
+        acc_add(F[1], t[1]);
+        if (D == 3) {
+            const double rz = ndisp(a.g, 2, iz, xp2);
+            acc_add(F[2], t[2]);
+            acc_add(T[0], ry * t[2] - rz * t[1]);
+            acc_add(T[1], rz * t[0] - rx * t[2]);
+            acc_add(T[2], rx * t[1] - ry * t[0]);
+        } else {
+            acc_add(T[2], rx * t[1] - ry * t[0]);
+        }
+    }
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) {
+#pragma unroll
+        for (int d = 0; d < 3; d++) {
+            Acc o;
+            o.s = shfl_xor_d(F[d].s, m);
+            o.c = shfl_xor_d(F[d].c, m);
+            acc_merge(F[d], o);
+            o.s = shfl_xor_d(T[d].s, m);
+            o.c = shfl_xor_d(T[d].c, m);
+            acc_merge(T[d], o);
+        }
+    }
+    if (lane == 0) {
+        for (int d = 0; d < 3; d++) {
+            double fv = -(F[d].s + F[d].c);
+            double tv = -(T[d].s + T[d].c);
+            if (D == 2 && d == 2) fv = 0.0;
+            if (D == 2 && d < 2) tv = 0.0;
+            a.P.Fh[d * P + p] = fv;
+            a.P.Th[d * P + p] = tv;
+        }
+    }
+}
+
+// ------------------------------------------------------------- cell list
+__device__ __forceinline__ int cell_coord(const CellArgs &a, int axis, double x) {
+    const int nc = axis == 0 ? a.ncx : (axis == 1 ? a.ncy : a.ncz);
+    const double L = axis == 0 ? a.g.Lx : (axis == 1 ? a.g.Ly : a.g.Lz);
+    double t = x;
+    if (axis == 1 && a.g.wall_y) t = x + 0.5;
+    int c = (int)floor(t * (double)nc / L);
+    return c < 0 ? 0 : (c >= nc ? nc - 1 : c);
+}
+
+__global__ void k_cells(CellArgs a) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    const int P = a.P.np;
+    if (p >= P) return;
+    const int cx = cell_coord(a, 0, a.P.x[p]);
+    const int cy = cell_coord(a, 1, a.P.x[P + p]);
+    const int cz = a.D == 3 ? cell_coord(a, 2, a.P.x[2 * P + p]) : 0;
+    const int c = cx + a.ncx * (cy + a.ncy * cz);
+    const int slot = atomicAdd(&a.cell_count[c], 1);
+    if (slot < CELL_CAP) a.cell_ids[c * CELL_CAP + slot] = p;
+    else atomicOr(a.flags, FLAG_CELL_OVERFLOW);
+}
+
+// Neighbour cell offsets along one axis: {-1,0,1} wrapped (periodic, >= 3
+// cells), {0,1} (2 cells), {0} (1 cell), or {-1,0,1} clipped at walls.
+__device__ __forceinline__ int axis_cells(int c, int nc, bool periodic, int out[3]) {
+    if (periodic) {
+        if (nc >= 3) { out[0] = c == 0 ? nc - 1 : c - 1; out[1] = c; out[2] = c == nc - 1 ? 0 : c + 1; return 3; }
+        if (nc == 2) { out[0] = 0; out[1] = 1; return 2; }
+        out[0] = 0;
+        return 1;
+    }
+    int k = 0;
+    for (int d = -1; d <= 1; d++)
+        if (c + d >= 0 && c + d < nc) out[k++] = c + d;
+    return k;
+}
+
+// Contact test and force of Eqs. 4-5 for the pair (i, j) with the overlap
+// delta = R_i + R_j - |r_i - r_j| (minimum image).  Returns false when the
+// particles do not touch.
+__device__ __forceinline__ bool pair_force(const CellArgs &a, int i, int j, double F[3]) {
+    const int P = a.P.np, D = a.D;
+    double d[3] = {0.0, 0.0, 0.0};
+    for (int ax = 0; ax < D; ax++) {
+        double dd = a.P.x[ax * P + i] - a.P.x[ax * P + j];
+        if (!(ax == 1 && a.g.wall_y)) dd = pdisp(dd, ax == 0 ? a.g.Lx : (ax == 1 ? a.g.Ly : a.g.Lz));
+        d[ax] = dd;
+    }
+    double d2 = d[0] * d[0] + d[1] * d[1];
+    if (D == 3) d2 = d2 + d[2] * d[2];
+    const double dist = sqrt(d2);
+    const double delta = (a.P.R[i] + a.P.R[j]) - dist;
+    if (!(delta > 0.0)) return false;
+    if (F) {
+        double nrm[3] = {0.0, 0.0, 0.0};
+        for (int ax = 0; ax < D; ax++) nrm[ax] = d[ax] / dist;
+        double vn = (a.P.v[i] - a.P.v[j]) * nrm[0] + (a.P.v[P + i] - a.P.v[P + j]) * nrm[1];
+        if (D == 3) vn = vn + (a.P.v[2 * P + i] - a.P.v[2 * P + j]) * nrm[2];
+        const double meff = a.P.m[i] * a.P.m[j] / (a.P.m[i] + a.P.m[j]);
+        const double eta = a.ce * sqrt(meff * a.kn);
+        const double fmag = a.kn * delta - eta * vn;
+        for (int ax = 0; ax < D; ax++) F[ax] = F[ax] + fmag * nrm[ax];
+    }
+    return true;
+}
+
+// One thread per particle: collect touching neighbours from the 3^D cells,
+// sort them by id and add the pair forces in ascending id, then the walls.
+__global__ void k_dem(CellArgs a) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int P = a.P.np;
+    if (i >= P) return;
+    const int D = a.D;
+    const int c0 = cell_coord(a, 0, a.P.x[i]);
+    const int c1 = cell_coord(a, 1, a.P.x[P + i]);
+    const int c2 = D == 3 ? cell_coord(a, 2, a.P.x[2 * P + i]) : 0;
+    int ox[3], oy[3], oz[3];
+    const int nxc = axis_cells(c0, a.ncx, true, ox);
+    const int nyc = axis_cells(c1, a.ncy, !a.g.wall_y, oy);
+    int nzc = 1;
+    oz[0] = 0;
+    if (D == 3) nzc = axis_cells(c2, a.ncz, true, oz);
+    int list[MAX_CONTACTS];
+    int nl = 0;
+    for (int kz = 0; kz < nzc; kz++)
+        for (int ky = 0; ky < nyc; ky++)
+            for (int kx = 0; kx < nxc; kx++) {
+                const int c = ox[kx] + a.ncx * (oy[ky] + a.ncy * oz[kz]);
+                const int cnt = min(a.cell_count[c], CELL_CAP);
+                for (int s = 0; s < cnt; s++) {
+                    const int j = a.cell_ids[c * CELL_CAP + s];
+                    if (j == i) continue;
+                    if (!pair_force(a, i, j, nullptr)) continue;
+                    if (nl < MAX_CONTACTS) list[nl++] = j;
+                    else atomicOr(a.flags, FLAG_CONTACT_OVERFLOW);
+                }
+            }
+    for (int s = 1; s < nl; s++) {
+        const int v = list[s];
+        int t = s - 1;
+        while (t >= 0 && list[t] > v) {
+            list[t + 1] = list[t];
+            t--;
+        }
+        list[t + 1] = v;
+    }
+    double F[3] = {0.0, 0.0, 0.0};
+    for (int s = 0; s < nl; s++) pair_force(a, i, list[s], F);
+    if (a.g.wall_y) {
+        const double eta = a.ce * sqrt(a.P.m[i] * a.kn);
+        const double y = a.P.x[P + i];
+        const double vy = a.P.v[P + i];
+        const double dl = a.P.R[i] - (y + 0.5);
+        if (dl > 0.0) {
+            const double fmag = a.kn * dl - eta * vy;
+            F[1] = F[1] + fmag;
+        }
+        const double du = a.P.R[i] - ((a.g.Ly - 0.5) - y);
+        if (du > 0.0) {
+            const double fmag = a.kn * du - eta * (-vy);
+            F[1] = F[1] - fmag;
+        }
+    }
+    for (int d = 0; d < 3; d++) a.P.Fc[d * P + i] = F[d];
+}
+
+__device__ __forceinline__ double wrap_pos(double x, double L) {
+    if (x < 0.0) {
+        x = x + L;
+        if (x >= L) x = x - L;
+    } else if (x >= L) {
+        x = x - L;
+    }
+    return x;
+}
+
+// Symplectic Euler with dt = 1: v += (F^h + F^c + m a)/m, omega += T^h/I,
+// x += v (new), periodic wrap.
+__global__ void k_integrate(CellArgs a) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    const int P = a.P.np;
+    if (p >= P || a.P.fixed[p]) return;
+    const int D = a.D;
+    const double m = a.P.m[p];
+    for (int d = 0; d < D; d++) {
+        const double ftot = a.P.Fh[d * P + p] + a.P.Fc[d * P + p] + m * a.ap[d];
+        a.P.v[d * P + p] = a.P.v[d * P + p] + ftot / m;
+    }
+    if (D == 3) {
+        for (int d = 0; d < 3; d++) a.P.w[d * P + p] = a.P.w[d * P + p] + a.P.Th[d * P + p] / a.P.I[p];
+    } else {
+        a.P.w[2 * P + p] = a.P.w[2 * P + p] + a.P.Th[2 * P + p] / a.P.I[p];
+    }
+    for (int d = 0; d < D; d++) {
+        double xn = a.P.x[d * P + p] + a.P.v[d * P + p];
+        if (!(d == 1 && a.g.wall_y)) xn = wrap_pos(xn, d == 0 ? a.g.Lx : (d == 1 ? a.g.Ly : a.g.Lz));
+        a.P.x[d * P + p] = xn;
+    }
+}
+
+// ---------------------------------------------------------------- launchers
+static unsigned blocks_for(int n, int per) { return (unsigned)((n + per - 1) / per); }
+
+hipError_t launch_foot_bbox(const FootArgs &a, int D, hipStream_t s) {
+    if (a.P.np == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_foot_bbox, dim3(blocks_for(a.P.np, 256)), dim3(256), 0, s, a, D);
+    return hipGetLastError();
+}
+
+hipError_t launch_foot_clear(const FootArgs &a, hipStream_t s) {
+    if (a.P.np == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_foot_clear, dim3((unsigned)a.P.np), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_foot_paint(const FootArgs &a, int D, hipStream_t s) {
+    if (a.P.np == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_foot_paint, dim3((unsigned)a.P.np), dim3(256), 0, s, a, D);
+    return hipGetLastError();
+}
+
+hipError_t launch_force(const ForceArgs &a, hipStream_t s) {
+    if (a.P.np == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_force, dim3(blocks_for(a.P.np, 4)), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_cells(const CellArgs &a, hipStream_t s) {
+    if (a.P.np == 0) return hipSuccess;
+    hipError_t e = launch_fill_u32((uint32_t *)a.cell_count, 0u, (int64_t)a.ncx * a.ncy * a.ncz, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_cells, dim3(blocks_for(a.P.np, 256)), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_dem(const CellArgs &a, hipStream_t s) {
+    if (a.P.np == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_dem, dim3(blocks_for(a.P.np, 128)), dim3(128), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_integrate(const CellArgs &a, hipStream_t s) {
+    if (a.P.np == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_integrate, dim3(blocks_for(a.P.np, 256)), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+}  // namespace lbimb

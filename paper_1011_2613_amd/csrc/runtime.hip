@@ -1,0 +1,861 @@
+// runtime.hip -- host side of liblbimb.so: the C ABI of include/lbimb.h.
+//
+// The caller hands over one device workspace; the context carves it into the
+// population arrays, footprint records, particle arrays and cell list and
+// never allocates device memory on the step path.  A step is a fixed sequence
+// of kernels on the context's stream; runs of steps replay a captured HIP
+// graph of two steps (one A->B->A swap), so small lattices are not
+// launch-bound.
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/lbimb.h"
+#include "internal.h"
+
+using namespace lbimb;
+
+namespace {
+
+constexpr size_t ALIGN = 256;
+constexpr uint64_t SAVE_MAGIC = 0x314d4942494d424cull;  // "LBMIBIM1"
+
+size_t align_up(size_t v) { return (v + ALIGN - 1) / ALIGN * ALIGN; }
+
+int store_bytes(int storage) { return storage == LBM_FP64 ? 8 : (storage == LBM_FP32_SHIFTED ? 4 : 2); }
+
+struct Layout {
+    int D, Q, Smax;
+    int64_t N;
+    int P;
+    int64_t cell_budget;
+    size_t off_fA, off_fB, off_nown, off_slots, off_q, off_beta, off_arel;
+    size_t off_x, off_v, off_w, off_R, off_m, off_I, off_fixed, off_Fh, off_Th, off_Fc, off_bb;
+    size_t off_cc, off_cid, off_flags, total;
+};
+
+int validate(const lbm_config *c, std::string &msg) {
+    if (!c) { msg = "null config"; return LBM_E_INVALID; }
+    if (c->lattice != LBM_D2Q9 && c->lattice != LBM_D3Q19) { msg = "lattice must be D2Q9 or D3Q19"; return LBM_E_INVALID; }
+    if (c->storage < LBM_FP64 || c->storage > LBM_FP16_STORE) { msg = "unknown storage"; return LBM_E_INVALID; }
+    if (c->nx < 1 || c->ny < 1 || c->nz < 1) { msg = "lattice sizes must be >= 1"; return LBM_E_INVALID; }
+    if (c->lattice == LBM_D2Q9 && c->nz != 1) { msg = "D2Q9 needs nz == 1"; return LBM_E_INVALID; }
+    if (c->ny > 65535 || c->nz > 65535) { msg = "ny and nz must be <= 65535"; return LBM_E_INVALID; }
+    if ((int64_t)c->nx * c->ny * c->nz >= ((int64_t)1 << 40)) { msg = "lattice too large"; return LBM_E_INVALID; }
+    if (!(c->tau > 0.5) || !std::isfinite(c->tau)) { msg = "tau must be > 1/2"; return LBM_E_INVALID; }
+    if (c->eps_samples < 1 || c->eps_samples > 8) { msg = "eps_samples must be in 1..8"; return LBM_E_INVALID; }
+    if (c->max_particles < 0 || c->max_particles > LBM_MAX_PARTICLES) { msg = "max_particles out of range"; return LBM_E_INVALID; }
+    if (!(c->restitution > 0.0 && c->restitution <= 1.0)) { msg = "restitution must be in (0, 1]"; return LBM_E_INVALID; }
+    if (!(c->kn >= 0.0)) { msg = "kn must be >= 0"; return LBM_E_INVALID; }
+    for (int a = 0; a < 3; a++)
+        if (!std::isfinite(c->fluid_force[a]) || !std::isfinite(c->particle_accel[a])) {
+            msg = "non-finite force"; return LBM_E_INVALID;
+        }
+    return LBM_OK;
+}
+
+Layout make_layout(const lbm_config *c) {
+    Layout L{};
+    L.D = c->lattice == LBM_D2Q9 ? 2 : 3;
+    L.Q = c->lattice == LBM_D2Q9 ? 9 : 19;
+    L.Smax = L.D == 2 ? c->eps_samples * c->eps_samples : c->eps_samples * c->eps_samples * c->eps_samples;
+    L.N = (int64_t)c->nx * c->ny * c->nz;
+    L.P = c->max_particles > 0 ? c->max_particles : 1;
+    L.cell_budget = std::max<int64_t>(65536, 8 * (int64_t)L.P);
+    const size_t fs = (size_t)L.Q * (size_t)L.N * store_bytes(c->storage);
+    size_t o = 0;
+    auto take = [&](size_t bytes) { size_t r = o; o = align_up(o + bytes); return r; };
+    L.off_fA = take(fs);
+    L.off_fB = take(fs);
+    L.off_nown = take(((size_t)L.N + 3) / 4 * 4);
+    L.off_slots = take((size_t)MAX_OWNERS * L.N * 4);
+    L.off_q = take((size_t)L.D * L.N * 8);
+    L.off_beta = take((size_t)(L.Smax + 1) * 8);
+    L.off_arel = take((size_t)(L.Smax + 1) * 8);
+    const size_t P = (size_t)L.P;
+    L.off_x = take(3 * P * 8);
+    L.off_v = take(3 * P * 8);
+    L.off_w = take(3 * P * 8);
+    L.off_R = take(P * 8);
+    L.off_m = take(P * 8);
+    L.off_I = take(P * 8);
+    L.off_fixed = take(P);
+    L.off_Fh = take(3 * P * 8);
+    L.off_Th = take(3 * P * 8);
+    L.off_Fc = take(3 * P * 8);
+    L.off_bb = take(6 * P * 4);
+    L.off_cc = take((size_t)L.cell_budget * 4);
+    L.off_cid = take((size_t)L.cell_budget * CELL_CAP * 4);
+    L.off_flags = take(64);
+    L.total = o;
+    return L;
+}
+
+struct TimedEvent {
+    int phase;
+    hipEvent_t a, b;
+};
+
+}  // namespace
+
+struct lbm_ctx {
+    lbm_config cfg;
+    Layout L;
+    char *ws;
+    hipStream_t stream;
+    hipStream_t cap_stream;
+    int cur;  // 0: state in fA, 1: state in fB
+    int64_t t;
+    int np;
+    bool particles_set;
+    Geom g;
+    int ncx, ncy, ncz;
+    double ce, arel0;
+    double cg[19];
+    hipGraphExec_t graph[2];
+    bool graph_ok[2];
+    bool timing;
+    std::vector<TimedEvent> events;
+    size_t ev_used;
+    double phase_ms[LBM_NPHASES];
+    int64_t phase_n[LBM_NPHASES];
+    char err[512];
+};
+
+namespace {
+
+template <class T> T *wsp(lbm_ctx *c, size_t off) { return (T *)(c->ws + off); }
+
+thread_local char g_err[512];  // last error of a call that has no context yet
+
+int fail(lbm_ctx *c, int code, const char *fmt, ...) {
+    char *dst = c ? c->err : g_err;
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(dst, 512, fmt, ap);
+    va_end(ap);
+    if (c) memcpy(g_err, c->err, sizeof(g_err));
+    return code;
+}
+
+#define HIPCHK(ctx, expr)                                                              \
+    do {                                                                               \
+        hipError_t e_ = (expr);                                                        \
+        if (e_ != hipSuccess) return fail(ctx, LBM_E_HIP, "%s: %s", #expr, hipGetErrorString(e_)); \
+    } while (0)
+
+Particles particles(lbm_ctx *c) {
+    Particles P;
+    P.x = wsp<double>(c, c->L.off_x);
+    P.v = wsp<double>(c, c->L.off_v);
+    P.w = wsp<double>(c, c->L.off_w);
+    P.R = wsp<double>(c, c->L.off_R);
+    P.m = wsp<double>(c, c->L.off_m);
+    P.I = wsp<double>(c, c->L.off_I);
+    P.fixed = wsp<uint8_t>(c, c->L.off_fixed);
+    P.Fh = wsp<double>(c, c->L.off_Fh);
+    P.Th = wsp<double>(c, c->L.off_Th);
+    P.Fc = wsp<double>(c, c->L.off_Fc);
+    P.bb = wsp<int>(c, c->L.off_bb);
+    P.np = c->np;
+    return P;
+}
+
+void *state(lbm_ctx *c, int which) { return c->ws + (which == 0 ? c->L.off_fA : c->L.off_fB); }
+
+uint32_t *flags(lbm_ctx *c) { return wsp<uint32_t>(c, c->L.off_flags); }
+
+CellArgs cell_args(lbm_ctx *c) {
+    CellArgs a;
+    a.P = particles(c);
+    a.g = c->g;
+    a.ncx = c->ncx; a.ncy = c->ncy; a.ncz = c->ncz;
+    a.cell_count = wsp<int>(c, c->L.off_cc);
+    a.cell_ids = wsp<int>(c, c->L.off_cid);
+    a.flags = flags(c);
+    a.D = c->L.D;
+    a.kn = c->cfg.kn;
+    a.ce = c->ce;
+    for (int d = 0; d < 3; d++) a.ap[d] = c->cfg.particle_accel[d];
+    return a;
+}
+
+FootArgs foot_args(lbm_ctx *c) {
+    FootArgs a;
+    a.P = particles(c);
+    a.g = c->g;
+    a.nown = wsp<uint8_t>(c, c->L.off_nown);
+    a.slots = wsp<uint32_t>(c, c->L.off_slots);
+    a.S = c->cfg.eps_samples;
+    a.flags = flags(c);
+    return a;
+}
+
+LBArgs lb_args(lbm_ctx *c, int from) {
+    LBArgs a;
+    a.A = state(c, from);
+    a.B = state(c, 1 - from);
+    a.nown = wsp<uint8_t>(c, c->L.off_nown);
+    a.slots = wsp<uint32_t>(c, c->L.off_slots);
+    a.beta_tab = wsp<double>(c, c->L.off_beta);
+    a.arel_tab = wsp<double>(c, c->L.off_arel);
+    a.q = wsp<double>(c, c->L.off_q);
+    a.px = wsp<double>(c, c->L.off_x);
+    a.pv = wsp<double>(c, c->L.off_v);
+    a.pw = wsp<double>(c, c->L.off_w);
+    a.np = c->np;
+    a.g = c->g;
+    a.Smax = c->L.Smax;
+    a.arel0 = c->arel0;
+    for (int i = 0; i < 19; i++) {
+        a.cg[i] = c->cg[i];
+        a.cgf[i] = (float)c->cg[i];
+    }
+    a.arel0f = (float)c->arel0;
+    a.tauf = (float)c->cfg.tau;
+    a.flags = flags(c);
+    return a;
+}
+
+// Phase markers for the timing mode.
+void phase_begin(lbm_ctx *c, int phase, hipStream_t s) {
+    if (!c->timing) return;
+    if (c->ev_used == c->events.size()) {
+        TimedEvent e{};
+        (void)hipEventCreate(&e.a);
+        (void)hipEventCreate(&e.b);
+        c->events.push_back(e);
+    }
+    c->events[c->ev_used].phase = phase;
+    (void)hipEventRecord(c->events[c->ev_used].a, s);
+}
+
+void phase_end(lbm_ctx *c, hipStream_t s) {
+    if (!c->timing) return;
+    (void)hipEventRecord(c->events[c->ev_used].b, s);
+    c->ev_used++;
+}
+
+// Queue one complete time step reading state `from`.
+hipError_t enqueue_step(lbm_ctx *c, int from, hipStream_t s) {
+    hipError_t e;
+    const int lattice = c->cfg.lattice, storage = c->cfg.storage;
+    if (c->np > 0) {
+        FootArgs fa = foot_args(c);
+        phase_begin(c, 0, s);
+        if ((e = launch_foot_clear(fa, s)) != hipSuccess) return e;
+        if ((e = launch_foot_paint(fa, c->L.D, s)) != hipSuccess) return e;
+        phase_end(c, s);
+    }
+    phase_begin(c, 1, s);
+    if ((e = launch_lb(lattice, storage, lb_args(c, from), s)) != hipSuccess) return e;
+    phase_end(c, s);
+    if (c->np > 0) {
+        ForceArgs fo;
+        fo.P = particles(c);
+        fo.g = c->g;
+        fo.nown = wsp<uint8_t>(c, c->L.off_nown);
+        fo.slots = wsp<uint32_t>(c, c->L.off_slots);
+        fo.q = wsp<double>(c, c->L.off_q);
+        fo.S = c->cfg.eps_samples;
+        fo.D = c->L.D;
+        phase_begin(c, 2, s);
+        if ((e = launch_force(fo, s)) != hipSuccess) return e;
+        phase_end(c, s);
+        CellArgs ca = cell_args(c);
+        phase_begin(c, 3, s);
+        if ((e = launch_cells(ca, s)) != hipSuccess) return e;
+        phase_end(c, s);
+        phase_begin(c, 4, s);
+        if ((e = launch_dem(ca, s)) != hipSuccess) return e;
+        phase_end(c, s);
+        phase_begin(c, 5, s);
+        if ((e = launch_integrate(ca, s)) != hipSuccess) return e;
+        phase_end(c, s);
+    }
+    return hipSuccess;
+}
+
+void drop_graphs(lbm_ctx *c) {
+    for (int k = 0; k < 2; k++) {
+        if (c->graph_ok[k]) (void)hipGraphExecDestroy(c->graph[k]);
+        c->graph_ok[k] = false;
+    }
+}
+
+int build_graph(lbm_ctx *c, int from) {
+    hipGraph_t graph;
+    HIPCHK(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
+    hipError_t e1 = enqueue_step(c, from, c->cap_stream);
+    hipError_t e2 = e1 == hipSuccess ? enqueue_step(c, 1 - from, c->cap_stream) : e1;
+    hipError_t e3 = hipStreamEndCapture(c->cap_stream, &graph);
+    if (e2 != hipSuccess) return fail(c, LBM_E_HIP, "graph capture: %s", hipGetErrorString(e2));
+    if (e3 != hipSuccess) return fail(c, LBM_E_HIP, "graph capture end: %s", hipGetErrorString(e3));
+    hipError_t e4 = hipGraphInstantiate(&c->graph[from], graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e4 != hipSuccess) return fail(c, LBM_E_HIP, "graph instantiate: %s", hipGetErrorString(e4));
+    c->graph_ok[from] = true;
+    return LBM_OK;
+}
+
+int check_flags(lbm_ctx *c) {
+    uint32_t h[4] = {0, 0, 0, 0};
+    HIPCHK(c, hipMemcpyAsync(h, flags(c), sizeof(h), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    if (h[0] & FLAG_SLOT_OVERFLOW)
+        return fail(c, LBM_E_SLOT_OVERFLOW, "more than %d particles cover one node", MAX_OWNERS);
+    if (h[0] & FLAG_CELL_OVERFLOW)
+        return fail(c, LBM_E_CELL_OVERFLOW, "a DEM cell holds more than %d particles", CELL_CAP);
+    if (h[0] & FLAG_CONTACT_OVERFLOW)
+        return fail(c, LBM_E_CONTACT_OVERFLOW, "a particle has more than %d contacts", MAX_CONTACTS);
+    if (h[0] & FLAG_NONFINITE) return fail(c, LBM_E_NONFINITE, "non-finite value in the state");
+    return LBM_OK;
+}
+
+// Runs `produce` into a device buffer (the caller's when ptr_kind is device,
+// else a temporary) and copies to the host when needed.
+template <class F>
+int produce_to(lbm_ctx *c, void *out, size_t bytes, int kind, F produce) {
+    if (kind != LBM_HOST && kind != LBM_DEVICE) return fail(c, LBM_E_INVALID, "bad ptr_kind");
+    if (!out) return fail(c, LBM_E_INVALID, "null output");
+    if (kind == LBM_DEVICE) {
+        HIPCHK(c, produce(out));
+        return LBM_OK;
+    }
+    void *tmp = nullptr;
+    HIPCHK(c, hipMalloc(&tmp, bytes));
+    hipError_t e = produce(tmp);
+    if (e == hipSuccess) e = hipMemcpyAsync(out, tmp, bytes, hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    (void)hipFree(tmp);
+    if (e != hipSuccess) return fail(c, LBM_E_HIP, "%s", hipGetErrorString(e));
+    return LBM_OK;
+}
+
+__global__ void k_masked_q(Geom g, int D, const uint8_t *nown, const double *q, double *out) {
+    const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= g.N) return;
+    const bool cov = nown[n] != 0;
+    for (int d = 0; d < D; d++) out[(int64_t)d * g.N + n] = cov ? q[(int64_t)d * g.N + n] : 0.0;
+}
+
+}  // namespace
+
+// ====================================================================== ABI
+extern "C" {
+
+const char *lbm_error_string(int code) {
+    switch (code) {
+        case LBM_OK: return "ok";
+        case LBM_E_INVALID: return "invalid argument";
+        case LBM_E_NOMEM: return "workspace too small";
+        case LBM_E_HIP: return "HIP runtime error";
+        case LBM_E_NONFINITE: return "non-finite value in the state";
+        case LBM_E_SLOT_OVERFLOW: return "too many particles cover one node";
+        case LBM_E_STATE: return "call out of order";
+        case LBM_E_IO: return "file error";
+        case LBM_E_CELL_OVERFLOW: return "DEM cell capacity exceeded";
+        case LBM_E_CONTACT_OVERFLOW: return "too many contacts on one particle";
+        default: return "unknown error";
+    }
+}
+
+const char *lbm_last_error(const lbm_ctx *ctx) { return ctx ? ctx->err : g_err; }
+
+int lbm_workspace_bytes(const lbm_config *cfg, size_t *bytes) {
+    std::string msg;
+    int rc = validate(cfg, msg);
+    if (rc != LBM_OK) return rc;
+    if (!bytes) return LBM_E_INVALID;
+    *bytes = make_layout(cfg).total;
+    return LBM_OK;
+}
+
+int lbm_create(const lbm_config *cfg, void *workspace, size_t ws_bytes, void *hip_stream,
+               lbm_ctx **out) {
+    if (!out) return LBM_E_INVALID;
+    *out = nullptr;
+    std::string msg;
+    int rc = validate(cfg, msg);
+    if (rc != LBM_OK) return fail(nullptr, rc, "%s", msg.c_str());
+    Layout L = make_layout(cfg);
+    if (!workspace || ws_bytes < L.total)
+        return fail(nullptr, LBM_E_NOMEM, "workspace of %zu bytes needed", L.total);
+    if (((uintptr_t)workspace) % ALIGN != 0) return fail(nullptr, LBM_E_INVALID, "workspace must be 256-byte aligned");
+    lbm_ctx *c = new (std::nothrow) lbm_ctx();
+    if (!c) return fail(nullptr, LBM_E_NOMEM, "host allocation failed");
+    c->cfg = *cfg;
+    c->L = L;
+    c->ws = (char *)workspace;
+    c->stream = (hipStream_t)hip_stream;
+    c->cur = 0;
+    c->t = 0;
+    c->np = 0;
+    c->particles_set = false;
+    c->g.nx = cfg->nx; c->g.ny = cfg->ny; c->g.nz = cfg->nz;
+    c->g.wall_y = cfg->wall_y ? 1 : 0;
+    c->g.N = L.N;
+    c->g.Lx = (double)cfg->nx; c->g.Ly = (double)cfg->ny; c->g.Lz = (double)cfg->nz;
+    c->ncx = c->ncy = c->ncz = 1;
+    const double le = std::log(cfg->restitution);
+    c->ce = -2.0 * le / std::sqrt(M_PI * M_PI + le * le);
+    c->arel0 = (1.0 - 0.0) / cfg->tau;
+    // c_i . g_fluid in the direction order of the lattice
+    const int *cx = cfg->lattice == LBM_D2Q9 ? D2Q9::cx : D3Q19::cx;
+    const int *cy = cfg->lattice == LBM_D2Q9 ? D2Q9::cy : D3Q19::cy;
+    const int *cz = cfg->lattice == LBM_D2Q9 ? D2Q9::cz : D3Q19::cz;
+    for (int i = 0; i < 19; i++) c->cg[i] = 0.0;
+    for (int i = 0; i < L.Q; i++) {
+        double v = (double)cx[i] * cfg->fluid_force[0] + (double)cy[i] * cfg->fluid_force[1];
+        if (L.D == 3) v = v + (double)cz[i] * cfg->fluid_force[2];
+        c->cg[i] = v;
+    }
+    c->graph_ok[0] = c->graph_ok[1] = false;
+    c->timing = false;
+    c->ev_used = 0;
+    for (int k = 0; k < LBM_NPHASES; k++) { c->phase_ms[k] = 0.0; c->phase_n[k] = 0; }
+    c->err[0] = 0;
+    if (hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking) != hipSuccess) {
+        delete c;
+        return fail(nullptr, LBM_E_HIP, "hipStreamCreateWithFlags failed");
+    }
+    // beta(eps) (Eq. 2) and (1 - beta)/tau for every possible clamped count
+    std::vector<double> beta(L.Smax + 1), arel(L.Smax + 1);
+    const double tau = cfg->tau;
+    for (int k = 0; k <= L.Smax; k++) {
+        const double eps = (double)k / (double)L.Smax;
+        beta[k] = eps * (tau - 0.5) / ((1.0 - eps) + (tau - 0.5));
+        arel[k] = (1.0 - beta[k]) / tau;
+    }
+    int r = LBM_OK;
+    auto chk = [&](hipError_t e) { if (e != hipSuccess && r == LBM_OK) r = fail(c, LBM_E_HIP, "%s", hipGetErrorString(e)); };
+    chk(hipMemcpyAsync(wsp<double>(c, L.off_beta), beta.data(), beta.size() * 8, hipMemcpyHostToDevice, c->stream));
+    chk(hipMemcpyAsync(wsp<double>(c, L.off_arel), arel.data(), arel.size() * 8, hipMemcpyHostToDevice, c->stream));
+    chk(launch_fill_u32(wsp<uint32_t>(c, L.off_nown), 0u, (int64_t)((L.N + 3) / 4), c->stream));
+    chk(launch_fill_u32(wsp<uint32_t>(c, L.off_flags), 0u, 16, c->stream));
+    chk(launch_fill_u32(wsp<uint32_t>(c, L.off_q), 0u, (int64_t)L.D * L.N * 2, c->stream));
+    // fluid at rest: f = f^eq(1, 0) = w_i  (shifted storage: g = 0)
+    {
+        const int Q = L.Q;
+        std::vector<double> wv(Q);
+        const double *w = cfg->lattice == LBM_D2Q9 ? D2Q9::w : D3Q19::w;
+        const int *wc = cfg->lattice == LBM_D2Q9 ? D2Q9::wc : D3Q19::wc;
+        for (int i = 0; i < Q; i++) wv[i] = w[wc[i]];
+        if (cfg->storage == LBM_FP64) {
+            // f^eq_i(1, 0) = w_i exactly (c.u = 0, u.u = 0)
+            for (int i = 0; i < Q; i++) {
+                uint64_t bits;
+                memcpy(&bits, &wv[i], 8);
+                chk(launch_fill_u64(wsp<uint64_t>(c, L.off_fA) + (size_t)i * L.N, bits, L.N, c->stream));
+            }
+        } else {
+            const size_t bytes = (size_t)Q * L.N * store_bytes(cfg->storage);
+            chk(launch_fill_u32(wsp<uint32_t>(c, L.off_fA), 0u, (int64_t)((bytes + 3) / 4), c->stream));
+        }
+    }
+    chk(hipStreamSynchronize(c->stream));
+    if (r != LBM_OK) {
+        (void)hipStreamDestroy(c->cap_stream);
+        delete c;
+        return r;  // message already in the thread's last error
+    }
+    *out = c;
+    return LBM_OK;
+}
+
+void lbm_destroy(lbm_ctx *c) {
+    if (!c) return;
+    (void)hipStreamSynchronize(c->stream);
+    drop_graphs(c);
+    for (auto &e : c->events) {
+        (void)hipEventDestroy(e.a);
+        (void)hipEventDestroy(e.b);
+    }
+    (void)hipStreamDestroy(c->cap_stream);
+    delete c;
+}
+
+int lbm_set_particles(lbm_ctx *c, int64_t n, const double *pos, const double *vel,
+                      const double *omega, const double *radius, const double *rho_s,
+                      const uint8_t *fixed, int ptr_kind) {
+    if (!c) return LBM_E_INVALID;
+    if (ptr_kind != LBM_HOST) return fail(c, LBM_E_INVALID, "lbm_set_particles takes host pointers");
+    if (n < 0 || n > c->cfg.max_particles) return fail(c, LBM_E_INVALID, "particle count %lld out of range", (long long)n);
+    if (n > 0 && (!pos || !vel || !omega || !radius || !rho_s))
+        return fail(c, LBM_E_INVALID, "null particle array");
+    const int D = c->L.D;
+    const double Lb[3] = {c->g.Lx, c->g.Ly, c->g.Lz};
+    double rmax = 0.0;
+    const int P = (int)n;
+    for (int p = 0; p < P; p++) {
+        const double r = radius[p];
+        if (!(r > 0.0) || !std::isfinite(r)) return fail(c, LBM_E_INVALID, "particle %d: radius must be > 0", p);
+        if (!(rho_s[p] > 0.0) || !std::isfinite(rho_s[p])) return fail(c, LBM_E_INVALID, "particle %d: density must be > 0", p);
+        for (int a = 0; a < D; a++) {
+            if (!std::isfinite(pos[3 * p + a]) || !std::isfinite(vel[3 * p + a]))
+                return fail(c, LBM_E_INVALID, "particle %d: non-finite state", p);
+            const bool periodic = !(a == 1 && c->g.wall_y);
+            if (periodic && (pos[3 * p + a] < 0.0 || pos[3 * p + a] >= Lb[a]))
+                return fail(c, LBM_E_INVALID, "particle %d: centre outside the periodic box", p);
+            if (periodic && 2.0 * r + 2.0 > Lb[a])
+                return fail(c, LBM_E_INVALID, "particle %d: wider than the periodic box", p);
+        }
+        if (c->g.wall_y && (pos[3 * p + 1] < -0.5 || pos[3 * p + 1] > Lb[1] - 0.5))
+            return fail(c, LBM_E_INVALID, "particle %d: centre beyond a wall", p);
+        rmax = std::max(rmax, r);
+    }
+    // DEM cells: edge >= 2 R_max, count bounded by the reserved budget
+    int nc[3] = {1, 1, 1};
+    if (P > 0) {
+        for (int a = 0; a < D; a++) nc[a] = std::max(1, (int)std::floor(Lb[a] / (2.0 * rmax)));
+        while ((int64_t)nc[0] * nc[1] * nc[2] > c->L.cell_budget)
+            for (int a = 0; a < D; a++) nc[a] = std::max(1, nc[a] / 2);
+    }
+    // overlap check on the host with the same cell grid
+    if (P > 1) {
+        const int ncell = nc[0] * nc[1] * nc[2];
+        std::vector<int> head(ncell, -1), next(P, -1);
+        auto cellof = [&](int p, int a) {
+            double t = pos[3 * p + a];
+            if (a == 1 && c->g.wall_y) t = t + 0.5;
+            int k = (int)std::floor(t * (double)nc[a] / Lb[a]);
+            return k < 0 ? 0 : (k >= nc[a] ? nc[a] - 1 : k);
+        };
+        for (int p = 0; p < P; p++) {
+            int ci[3] = {cellof(p, 0), cellof(p, 1), D == 3 ? cellof(p, 2) : 0};
+            const int id = ci[0] + nc[0] * (ci[1] + nc[1] * ci[2]);
+            next[p] = head[id];
+            head[id] = p;
+        }
+        for (int p = 0; p < P; p++) {
+            int ci[3] = {cellof(p, 0), cellof(p, 1), D == 3 ? cellof(p, 2) : 0};
+            for (int dz = (D == 3 ? -1 : 0); dz <= (D == 3 ? 1 : 0); dz++)
+                for (int dy = -1; dy <= 1; dy++)
+                    for (int dx = -1; dx <= 1; dx++) {
+                        int cc[3] = {ci[0] + dx, ci[1] + dy, ci[2] + dz};
+                        bool skip = false;
+                        for (int a = 0; a < 3; a++) {
+                            if (a == 1 && c->g.wall_y) { if (cc[a] < 0 || cc[a] >= nc[a]) skip = true; }
+                            else cc[a] = ((cc[a] % nc[a]) + nc[a]) % nc[a];
+                        }
+                        if (skip) continue;
+                        for (int q = head[cc[0] + nc[0] * (cc[1] + nc[1] * cc[2])]; q >= 0; q = next[q]) {
+                            if (q <= p) continue;
+                            double d2 = 0.0;
+                            for (int a = 0; a < D; a++) {
+                                double d = pos[3 * p + a] - pos[3 * q + a];
+                                if (!(a == 1 && c->g.wall_y)) {
+                                    if (d > 0.5 * Lb[a]) d -= Lb[a];
+                                    else if (d < -0.5 * Lb[a]) d += Lb[a];
+                                }
+                                d2 += d * d;
+                            }
+                            const double lim = radius[p] + radius[q] - 0.5 * std::min(radius[p], radius[q]);
+                            if (d2 < lim * lim)
+                                return fail(c, LBM_E_INVALID, "particles %d and %d overlap by more than half a radius", p, q);
+                        }
+                    }
+        }
+    }
+    const size_t Pc = (size_t)c->L.P;
+    std::vector<double> X(3 * Pc, 0.0), V(3 * Pc, 0.0), W(3 * Pc, 0.0), R(Pc, 0.0), M(Pc, 0.0), I(Pc, 0.0);
+    std::vector<uint8_t> F(Pc, 0);
+    for (int p = 0; p < P; p++) {
+        for (int a = 0; a < 3; a++) {
+            const bool used = a < D;
+            X[a * Pc + p] = used ? pos[3 * p + a] : 0.0;
+            V[a * Pc + p] = used ? vel[3 * p + a] : 0.0;
+            W[a * Pc + p] = (D == 3 || a == 2) ? omega[3 * p + a] : 0.0;
+        }
+        const double r = radius[p];
+        R[p] = r;
+        if (D == 2) {
+            M[p] = rho_s[p] * (M_PI * r * r);
+            I[p] = 0.5 * M[p] * r * r;
+        } else {
+            M[p] = rho_s[p] * (4.0 / 3.0 * M_PI * r * r * r);
+            I[p] = 0.4 * M[p] * r * r;
+        }
+        F[p] = fixed ? (fixed[p] ? 1 : 0) : 0;
+    }
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    drop_graphs(c);
+    // particle arrays are [3][np] on the device: compact to the actual count
+    const size_t np = (size_t)std::max(P, 1);
+    std::vector<double> Xc(3 * np, 0.0), Vc(3 * np, 0.0), Wc(3 * np, 0.0);
+    for (int a = 0; a < 3; a++)
+        for (int p = 0; p < P; p++) {
+            Xc[a * np + p] = X[a * Pc + p];
+            Vc[a * np + p] = V[a * Pc + p];
+            Wc[a * np + p] = W[a * Pc + p];
+        }
+    c->np = P;
+    HIPCHK(c, hipMemcpy(wsp<double>(c, c->L.off_x), Xc.data(), 3 * np * 8, hipMemcpyHostToDevice));
+    HIPCHK(c, hipMemcpy(wsp<double>(c, c->L.off_v), Vc.data(), 3 * np * 8, hipMemcpyHostToDevice));
+    HIPCHK(c, hipMemcpy(wsp<double>(c, c->L.off_w), Wc.data(), 3 * np * 8, hipMemcpyHostToDevice));
+    HIPCHK(c, hipMemcpy(wsp<double>(c, c->L.off_R), R.data(), np * 8, hipMemcpyHostToDevice));
+    HIPCHK(c, hipMemcpy(wsp<double>(c, c->L.off_m), M.data(), np * 8, hipMemcpyHostToDevice));
+    HIPCHK(c, hipMemcpy(wsp<double>(c, c->L.off_I), I.data(), np * 8, hipMemcpyHostToDevice));
+    HIPCHK(c, hipMemcpy(wsp<uint8_t>(c, c->L.off_fixed), F.data(), np, hipMemcpyHostToDevice));
+    c->ncx = nc[0]; c->ncy = nc[1]; c->ncz = nc[2];
+    // forget the old footprint, then record bounding boxes for the first clear
+    HIPCHK(c, launch_fill_u32(wsp<uint32_t>(c, c->L.off_nown), 0u, (int64_t)((c->L.N + 3) / 4), c->stream));
+    HIPCHK(c, launch_fill_u32(wsp<uint32_t>(c, c->L.off_Fh), 0u, (int64_t)(3 * np * 2), c->stream));
+    HIPCHK(c, launch_fill_u32(wsp<uint32_t>(c, c->L.off_Th), 0u, (int64_t)(3 * np * 2), c->stream));
+    HIPCHK(c, launch_fill_u32(wsp<uint32_t>(c, c->L.off_Fc), 0u, (int64_t)(3 * np * 2), c->stream));
+    HIPCHK(c, launch_foot_bbox(foot_args(c), D, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    c->particles_set = true;
+    return LBM_OK;
+}
+
+int lbm_set_distributions(lbm_ctx *c, const double *f, int ptr_kind) {
+    if (!c || !f) return LBM_E_INVALID;
+    const size_t bytes = (size_t)c->L.Q * c->L.N * 8;
+    const double *src = f;
+    void *tmp = nullptr;
+    if (ptr_kind == LBM_HOST) {
+        HIPCHK(c, hipMalloc(&tmp, bytes));
+        hipError_t e = hipMemcpy(tmp, f, bytes, hipMemcpyHostToDevice);
+        if (e != hipSuccess) { (void)hipFree(tmp); return fail(c, LBM_E_HIP, "%s", hipGetErrorString(e)); }
+        src = (const double *)tmp;
+    } else if (ptr_kind != LBM_DEVICE) {
+        return fail(c, LBM_E_INVALID, "bad ptr_kind");
+    }
+    hipError_t e = launch_set_f(c->cfg.lattice, c->cfg.storage, c->g, src, state(c, c->cur), c->stream);
+    if (e == hipSuccess && tmp) e = hipStreamSynchronize(c->stream);
+    if (tmp) (void)hipFree(tmp);
+    if (e != hipSuccess) return fail(c, LBM_E_HIP, "%s", hipGetErrorString(e));
+    return LBM_OK;
+}
+
+int lbm_get_distributions(lbm_ctx *c, double *f, int ptr_kind) {
+    if (!c) return LBM_E_INVALID;
+    const size_t bytes = (size_t)c->L.Q * c->L.N * 8;
+    return produce_to(c, f, bytes, ptr_kind, [&](void *dst) {
+        return launch_get_f(c->cfg.lattice, c->cfg.storage, c->g, state(c, c->cur), (double *)dst, c->stream);
+    });
+}
+
+int lbm_get_macro(lbm_ctx *c, double *rho, double *u, int ptr_kind) {
+    if (!c || !rho || !u) return LBM_E_INVALID;
+    const int64_t N = c->L.N;
+    if (ptr_kind == LBM_DEVICE) {
+        HIPCHK(c, launch_macro(c->cfg.lattice, c->cfg.storage, c->g, state(c, c->cur), rho, u, c->stream));
+        return LBM_OK;
+    }
+    if (ptr_kind != LBM_HOST) return fail(c, LBM_E_INVALID, "bad ptr_kind");
+    void *tmp = nullptr;
+    const size_t bytes = (size_t)(1 + c->L.D) * N * 8;
+    HIPCHK(c, hipMalloc(&tmp, bytes));
+    double *dr = (double *)tmp, *du = dr + N;
+    hipError_t e = launch_macro(c->cfg.lattice, c->cfg.storage, c->g, state(c, c->cur), dr, du, c->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(rho, dr, N * 8, hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(u, du, (size_t)c->L.D * N * 8, hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    (void)hipFree(tmp);
+    if (e != hipSuccess) return fail(c, LBM_E_HIP, "%s", hipGetErrorString(e));
+    return LBM_OK;
+}
+
+int lbm_get_q(lbm_ctx *c, double *q, int ptr_kind) {
+    if (!c) return LBM_E_INVALID;
+    const size_t bytes = (size_t)c->L.D * c->L.N * 8;
+    return produce_to(c, q, bytes, ptr_kind, [&](void *dst) {
+        const int64_t blocks = (c->L.N + 255) / 256;
+        hipLaunchKernelGGL(k_masked_q, dim3((unsigned)blocks), dim3(256), 0, c->stream, c->g, c->L.D,
+                           wsp<uint8_t>(c, c->L.off_nown), wsp<double>(c, c->L.off_q), (double *)dst);
+        return hipGetLastError();
+    });
+}
+
+static int get_particle_vec(lbm_ctx *c, size_t off, double *out, int ptr_kind) {
+    // device layout [3][np] -> caller layout [np][3]
+    const int P = c->np;
+    if (P == 0) return LBM_OK;
+    std::vector<double> h(3 * (size_t)P);
+    HIPCHK(c, hipMemcpyAsync(h.data(), wsp<double>(c, off), h.size() * 8, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    std::vector<double> t(3 * (size_t)P);
+    for (int p = 0; p < P; p++)
+        for (int a = 0; a < 3; a++) t[3 * p + a] = h[(size_t)a * P + p];
+    if (ptr_kind == LBM_HOST) {
+        memcpy(out, t.data(), t.size() * 8);
+    } else if (ptr_kind == LBM_DEVICE) {
+        HIPCHK(c, hipMemcpyAsync(out, t.data(), t.size() * 8, hipMemcpyHostToDevice, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+    } else {
+        return fail(c, LBM_E_INVALID, "bad ptr_kind");
+    }
+    return LBM_OK;
+}
+
+int lbm_get_forces(lbm_ctx *c, double *F, double *T, int ptr_kind) {
+    if (!c || (c->np > 0 && (!F || !T))) return LBM_E_INVALID;
+    int r = get_particle_vec(c, c->L.off_Fh, F, ptr_kind);
+    if (r != LBM_OK) return r;
+    return get_particle_vec(c, c->L.off_Th, T, ptr_kind);
+}
+
+int lbm_get_contact_forces(lbm_ctx *c, double *Fc, int ptr_kind) {
+    if (!c || (c->np > 0 && !Fc)) return LBM_E_INVALID;
+    return get_particle_vec(c, c->L.off_Fc, Fc, ptr_kind);
+}
+
+int lbm_get_particles(lbm_ctx *c, double *pos, double *vel, double *omega, int ptr_kind) {
+    if (!c || (c->np > 0 && (!pos || !vel || !omega))) return LBM_E_INVALID;
+    int r = get_particle_vec(c, c->L.off_x, pos, ptr_kind);
+    if (r == LBM_OK) r = get_particle_vec(c, c->L.off_v, vel, ptr_kind);
+    if (r == LBM_OK) r = get_particle_vec(c, c->L.off_w, omega, ptr_kind);
+    return r;
+}
+
+int64_t lbm_time(const lbm_ctx *c) { return c ? c->t : -1; }
+
+int64_t lbm_particle_count(const lbm_ctx *c) { return c ? c->np : -1; }
+
+int lbm_step(lbm_ctx *c, int64_t nsteps) {
+    if (!c || nsteps < 0) return LBM_E_INVALID;
+    if (nsteps == 0) return LBM_OK;
+    hipError_t e;
+    if (c->timing) {
+        for (int64_t k = 0; k < nsteps; k++) {
+            if ((e = enqueue_step(c, c->cur, c->stream)) != hipSuccess)
+                return fail(c, LBM_E_HIP, "step: %s", hipGetErrorString(e));
+            c->cur ^= 1;
+            c->t++;
+        }
+        return check_flags(c);
+    }
+    int64_t left = nsteps;
+    if (left >= 2) {
+        if (!c->graph_ok[c->cur]) {
+            int r = build_graph(c, c->cur);
+            if (r != LBM_OK) return r;
+        }
+        const int64_t pairs = left / 2;
+        for (int64_t k = 0; k < pairs; k++)
+            if ((e = hipGraphLaunch(c->graph[c->cur], c->stream)) != hipSuccess)
+                return fail(c, LBM_E_HIP, "graph launch: %s", hipGetErrorString(e));
+        c->t += 2 * pairs;
+        left -= 2 * pairs;
+    }
+    if (left == 1) {
+        if ((e = enqueue_step(c, c->cur, c->stream)) != hipSuccess)
+            return fail(c, LBM_E_HIP, "step: %s", hipGetErrorString(e));
+        c->cur ^= 1;
+        c->t++;
+    }
+    return check_flags(c);
+}
+
+int lbm_set_timing(lbm_ctx *c, int enable) {
+    if (!c) return LBM_E_INVALID;
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    c->timing = enable != 0;
+    c->ev_used = 0;
+    for (int k = 0; k < LBM_NPHASES; k++) { c->phase_ms[k] = 0.0; c->phase_n[k] = 0; }
+    return LBM_OK;
+}
+
+int lbm_get_timing(lbm_ctx *c, double *ms, int64_t *launches) {
+    if (!c || !ms || !launches) return LBM_E_INVALID;
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    for (size_t k = 0; k < c->ev_used; k++) {
+        float t = 0.0f;
+        HIPCHK(c, hipEventElapsedTime(&t, c->events[k].a, c->events[k].b));
+        c->phase_ms[c->events[k].phase] += (double)t;
+        c->phase_n[c->events[k].phase] += 1;
+    }
+    c->ev_used = 0;
+    for (int k = 0; k < LBM_NPHASES; k++) { ms[k] = c->phase_ms[k]; launches[k] = c->phase_n[k]; }
+    return LBM_OK;
+}
+
+int lbm_save(lbm_ctx *c, const char *path) {
+    if (!c || !path) return LBM_E_INVALID;
+    FILE *fp = fopen(path, "wb");
+    if (!fp) return fail(c, LBM_E_IO, "cannot open %s", path);
+    const size_t fbytes = (size_t)c->L.Q * c->L.N * store_bytes(c->cfg.storage);
+    const size_t P = (size_t)std::max(c->np, 1);
+    std::vector<char> buf(std::max(fbytes, 16 * P * 8));
+    bool ok = true;
+    auto put = [&](const void *p, size_t n) { ok = ok && fwrite(p, 1, n, fp) == n; };
+    put(&SAVE_MAGIC, 8);
+    put(&c->cfg, sizeof(lbm_config));
+    put(&c->t, 8);
+    put(&c->np, 4);
+    if (hipMemcpy(buf.data(), state(c, c->cur), fbytes, hipMemcpyDeviceToHost) != hipSuccess) ok = false;
+    put(buf.data(), fbytes);
+    const size_t offs[] = {c->L.off_x, c->L.off_v, c->L.off_w, c->L.off_Fh, c->L.off_Th, c->L.off_Fc};
+    for (size_t o : offs) {
+        if (hipMemcpy(buf.data(), c->ws + o, 3 * P * 8, hipMemcpyDeviceToHost) != hipSuccess) ok = false;
+        put(buf.data(), 3 * P * 8);
+    }
+    const size_t offs1[] = {c->L.off_R, c->L.off_m, c->L.off_I};
+    for (size_t o : offs1) {
+        if (hipMemcpy(buf.data(), c->ws + o, P * 8, hipMemcpyDeviceToHost) != hipSuccess) ok = false;
+        put(buf.data(), P * 8);
+    }
+    if (hipMemcpy(buf.data(), c->ws + c->L.off_fixed, P, hipMemcpyDeviceToHost) != hipSuccess) ok = false;
+    put(buf.data(), P);
+    put(&c->ncx, 4); put(&c->ncy, 4); put(&c->ncz, 4);
+    if (fclose(fp) != 0) ok = false;
+    return ok ? LBM_OK : fail(c, LBM_E_IO, "write failed: %s", path);
+}
+
+int lbm_load(lbm_ctx *c, const char *path) {
+    if (!c || !path) return LBM_E_INVALID;
+    FILE *fp = fopen(path, "rb");
+    if (!fp) return fail(c, LBM_E_IO, "cannot open %s", path);
+    bool ok = true;
+    auto get = [&](void *p, size_t n) { ok = ok && fread(p, 1, n, fp) == n; };
+    uint64_t magic = 0;
+    lbm_config cfg;
+    int64_t t = 0;
+    int np = 0;
+    get(&magic, 8);
+    get(&cfg, sizeof(cfg));
+    get(&t, 8);
+    get(&np, 4);
+    if (!ok || magic != SAVE_MAGIC) { fclose(fp); return fail(c, LBM_E_IO, "not a state file: %s", path); }
+    if (memcmp(&cfg, &c->cfg, sizeof(cfg)) != 0) { fclose(fp); return fail(c, LBM_E_INVALID, "state file has another configuration"); }
+    if (np < 0 || np > c->cfg.max_particles) { fclose(fp); return fail(c, LBM_E_INVALID, "bad particle count in file"); }
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    drop_graphs(c);
+    c->np = np;
+    const size_t fbytes = (size_t)c->L.Q * c->L.N * store_bytes(c->cfg.storage);
+    const size_t P = (size_t)std::max(np, 1);
+    std::vector<char> buf(std::max(fbytes, 16 * P * 8));
+    get(buf.data(), fbytes);
+    if (ok && hipMemcpy(state(c, 0), buf.data(), fbytes, hipMemcpyHostToDevice) != hipSuccess) ok = false;
+    const size_t offs[] = {c->L.off_x, c->L.off_v, c->L.off_w, c->L.off_Fh, c->L.off_Th, c->L.off_Fc};
+    for (size_t o : offs) {
+        get(buf.data(), 3 * P * 8);
+        if (ok && hipMemcpy(c->ws + o, buf.data(), 3 * P * 8, hipMemcpyHostToDevice) != hipSuccess) ok = false;
+    }
+    const size_t offs1[] = {c->L.off_R, c->L.off_m, c->L.off_I};
+    for (size_t o : offs1) {
+        get(buf.data(), P * 8);
+        if (ok && hipMemcpy(c->ws + o, buf.data(), P * 8, hipMemcpyHostToDevice) != hipSuccess) ok = false;
+    }
+    get(buf.data(), P);
+    if (ok && hipMemcpy(c->ws + c->L.off_fixed, buf.data(), P, hipMemcpyHostToDevice) != hipSuccess) ok = false;
+    get(&c->ncx, 4); get(&c->ncy, 4); get(&c->ncz, 4);
+    fclose(fp);
+    if (!ok) return fail(c, LBM_E_IO, "read failed: %s", path);
+    c->cur = 0;
+    c->t = t;
+    c->particles_set = true;
+    HIPCHK(c, launch_fill_u32(wsp<uint32_t>(c, c->L.off_nown), 0u, (int64_t)((c->L.N + 3) / 4), c->stream));
+    HIPCHK(c, launch_foot_bbox(foot_args(c), c->L.D, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return LBM_OK;
+}
+
+}  // extern "C"

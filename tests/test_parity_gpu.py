@@ -1,0 +1,254 @@
+"""Parity of the HIP path (through the C ABI) against the FP64 CPU oracle.
+
+FP64 bar: every field within 1e-12 relative (max |gpu - oracle| / max |oracle|)
+after the stated number of steps.  Both sides evaluate every per-node formula
+in the same order without fused multiply-add, and the per-particle sums are
+compensated, so in practice the fields agree bit for bit; the tests report the
+largest error seen.
+"""
+import math
+import os
+import tempfile
+
+import numpy as np
+import pytest
+
+from paper_1011_2613_amd import inputs as I
+from tests.parity_util import compare, make_pair, rel_err, seeded_f
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-12
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def assert_close(errs, tol=TOL, label=""):
+    say(label, {k: "%.2e" % v for k, v in errs.items()})
+    bad = {k: v for k, v in errs.items() if not (v <= tol)}
+    assert not bad, "%s exceeds %g: %s" % (label, tol, bad)
+
+
+def c1_particles():
+    w = I.workload("C1")
+    return w, w.particles()
+
+
+# ------------------------------------------------------------------ C1 (D2Q9)
+def test_c1_one_step_bitwise(gpu_lib):
+    w, parts = c1_particles()
+    say("C1 one step", w.shape)
+    orc, gpu = make_pair(gpu_lib, 2, w.shape, w.tau, fluid_force=w.fluid_force, samples=w.samples,
+                         kn=w.kn, restitution=w.restitution, particles=parts)
+    orc.step(1)
+    gpu.step(1)
+    assert np.array_equal(gpu.get_f(), orc.get_f())
+    assert np.array_equal(gpu.q(), orc.q()[:2])
+    F0, T0 = orc.forces()
+    F1, T1 = gpu.forces()
+    assert np.array_equal(F1, F0) and np.array_equal(T1, T0)
+
+
+def test_c1_full_run(gpu_lib):
+    """C1: D2Q9 256x256, tau 0.6, fluid force 1e-6, 16 discs R=6, 1000 steps."""
+    w, parts = c1_particles()
+    say("C1 full", w.shape, w.steps)
+    orc, gpu = make_pair(gpu_lib, 2, w.shape, w.tau, fluid_force=w.fluid_force, samples=w.samples,
+                         kn=w.kn, restitution=w.restitution, particles=parts)
+    for chunk in (1, 99, 400, 500):
+        orc.step(chunk)
+        gpu.step(chunk)
+        errs = compare(orc, gpu)
+        assert_close(errs, label="C1 t=%d" % orc.t)
+    # the discs have been dragged along +x by the flow
+    x0 = parts[0]
+    x1, _, _ = gpu.particles()
+    assert np.all(((x1[:, 0] - x0[:, 0]) % 256.0) > 0)
+
+
+# ------------------------------------------------------- D3Q19 with walls
+def spheres(box, R, n, seed, v0, wall_y=True, rho=5.0):
+    pos = I.place_particles(3, box, R, n, seed, wall_y=wall_y)
+    vel = I.random_velocities(3, n, v0, seed + 1)
+    om = I.random_velocities(3, n, 1e-3, seed + 2)
+    return pos, vel, om, np.full(n, R), np.full(n, rho), np.zeros(n, np.uint8)
+
+
+def test_d3q19_walls_moving_spheres(gpu_lib):
+    box = (40, 36, 24)
+    parts = spheres(box, 4.0, 8, 31, 0.01)
+    say("D3Q19 walls", box)
+    orc, gpu = make_pair(gpu_lib, 3, box, 0.62, wall_y=True, fluid_force=(2e-6, 0, 1e-6),
+                         particle_accel=(0, -2e-5, 0), samples=4, kn=500.0, restitution=0.8,
+                         particles=parts)
+    for chunk in (1, 60, 140):
+        orc.step(chunk)
+        gpu.step(chunk)
+        assert_close(compare(orc, gpu), label="D3Q19 walls t=%d" % orc.t)
+
+
+@pytest.mark.parametrize("dim,shape,wall", [(2, (100, 37), True), (2, (67, 70), False),
+                                            (3, (70, 19, 13), True), (3, (33, 30, 29), False)])
+def test_ragged_random_state(gpu_lib, dim, shape, wall):
+    """Seeded random populations on ragged lattices (not multiples of the
+    wavefront), with particles, both boundary kinds."""
+    N = int(np.prod(shape))
+    f0 = seeded_f(dim, N, 0.02, 77 + N)
+    R = 3.0
+    n = 4
+    pos = I.place_particles(dim, shape, R, n, 5 + N, wall_y=wall)
+    vel = I.random_velocities(dim, n, 0.01, 9)
+    om = np.zeros((n, 3)); om[:, 2] = 2e-3
+    if dim == 3:
+        om = I.random_velocities(3, n, 2e-3, 11)
+    parts = (pos, vel, om, np.full(n, R), np.full(n, 3.0), np.array([0, 1, 0, 0], np.uint8))
+    say("ragged", dim, shape, wall)
+    orc, gpu = make_pair(gpu_lib, dim, shape, 0.55, wall_y=wall, fluid_force=(1e-5, -3e-6, 2e-6),
+                         particle_accel=(0, -1e-5, 0), samples=3, kn=300.0, restitution=0.7,
+                         particles=parts, f0=f0)
+    assert_close(compare(orc, gpu), label="ragged t=0")
+    for chunk in (1, 30):
+        orc.step(chunk)
+        gpu.step(chunk)
+        assert_close(compare(orc, gpu), label="ragged t=%d" % orc.t)
+
+
+def hex_pack(box, R, rows, gap=-0.2, y0=None, seed=0, v=0.01):
+    """Discs in a hexagonal packing resting on the lower wall, neighbours
+    overlapping by -gap, with seeded random velocities."""
+    s = 2 * R + gap
+    per_row = int(box[0] // s)
+    pos = []
+    for r in range(rows):
+        y = (R - 0.6 if y0 is None else y0) + r * s * math.sqrt(3) / 2
+        for k in range(per_row):
+            pos.append([(0.5 * s * (r % 2) + 1.0 + k * s) % box[0], y, 0.0])
+    pos = np.array(pos)
+    n = len(pos)
+    vel = I.random_velocities(2, n, v, seed)
+    return pos, vel
+
+
+def test_dense_dem_contacts(gpu_lib):
+    """Discs packed in contact on the lower wall, gravity: pair contacts, the
+    periodic seam, the wall and the cell list must reproduce the oracle's
+    all-pairs search step by step."""
+    box = (96, 64)
+    R = 4.0
+    pos, vel = hex_pack(box, R, 4, seed=124)
+    n = len(pos)
+    parts = (pos, vel, np.zeros((n, 3)), np.full(n, R), np.full(n, 10.0), np.zeros(n, np.uint8))
+    say("dense DEM", box, n)
+    orc, gpu = make_pair(gpu_lib, 2, box, 0.7, wall_y=True, particle_accel=(0, -1e-4, 0),
+                         samples=4, kn=200.0, restitution=0.9, particles=parts)
+    contacts = []
+    for chunk in (1, 9, 40, 150):
+        orc.step(chunk)
+        gpu.step(chunk)
+        contacts.append(int(np.count_nonzero(np.abs(orc.contact_forces()).sum(axis=1))))
+        assert_close(compare(orc, gpu), label="dense DEM t=%d contacts %d" % (orc.t, contacts[-1]))
+    assert contacts[0] == n and min(contacts) >= 5
+
+
+def test_pure_fluid_no_particles(gpu_lib):
+    for dim, shape in ((2, (64, 24)), (3, (20, 16, 12))):
+        say("pure fluid", dim, shape)
+        f0 = seeded_f(dim, int(np.prod(shape)), 0.01, 3)
+        orc, gpu = make_pair(gpu_lib, dim, shape, 0.8, wall_y=True, fluid_force=(1e-5, 0, 0), f0=f0)
+        orc.step(50)
+        gpu.step(50)
+        assert_close(compare(orc, gpu), label="fluid %dD" % dim)
+
+
+# ----------------------------------------------------------- runtime paths
+def test_graph_and_eager_agree_bitwise(gpu_lib):
+    """Graph replay (timing off) and one-by-one launches (timing on) give the
+    same state bit for bit; two runs are identical (no races)."""
+    w, parts = c1_particles()
+    say("graph vs eager")
+    sims = []
+    for timing in (False, True, False):
+        s = gpu_lib.Simulation(2, w.shape, w.tau, fluid_force=w.fluid_force, samples=w.samples,
+                               kn=w.kn, restitution=w.restitution, max_particles=16)
+        s.set_particles(*parts)
+        s.set_timing(timing)
+        s.step(37)
+        sims.append(s)
+    f = [s.get_f() for s in sims]
+    assert np.array_equal(f[0], f[1]) and np.array_equal(f[0], f[2])
+    t = sims[1].get_timing()
+    assert t["lattice"][1] == 37 and t["lattice"][0] > 0
+
+
+def test_save_load_resume_bitwise(gpu_lib):
+    box = (40, 36, 24)
+    parts = spheres(box, 4.0, 6, 41, 0.01)
+    say("save/load")
+    kw = dict(storage="fp64", wall_y=True, fluid_force=(1e-6, 0, 0), particle_accel=(0, -1e-5, 0),
+              samples=4, kn=500.0, restitution=0.8, max_particles=6)
+    a = gpu_lib.Simulation(3, box, 0.6, **kw)
+    a.set_particles(*parts)
+    a.step(40)
+    b = gpu_lib.Simulation(3, box, 0.6, **kw)
+    b.set_particles(*parts)
+    b.step(20)
+    with tempfile.TemporaryDirectory() as d:
+        p = os.path.join(d, "state.bin")
+        b.save(p)
+        c = gpu_lib.Simulation(3, box, 0.6, **kw)
+        c.load_state(p)
+    c.step(20)
+    assert c.t == 40
+    assert np.array_equal(a.get_f(), c.get_f())
+    assert np.array_equal(a.particles()[0], c.particles()[0])
+
+
+def test_slot_overflow_is_reported(gpu_lib):
+    """Five spheres around one node (triangular bipyramid, overlaps below half
+    a radius): the node has more owners than the library keeps."""
+    R, r = 4.0, 4.3
+    c = np.array([12.0, 12.0, 12.0])
+    dirs = [(0, 0, 1), (0, 0, -1)] + [(math.cos(a), math.sin(a), 0) for a in
+                                     (0.0, 2 * math.pi / 3, 4 * math.pi / 3)]
+    pos = np.array([c + r * np.array(d) for d in dirs])
+    say("slot overflow")
+    s = gpu_lib.Simulation(3, (24, 24, 24), 0.7, samples=4, kn=10.0, max_particles=5)
+    s.set_particles(pos, radius=np.full(5, R), rho_s=np.full(5, 2.0))
+    with pytest.raises(gpu_lib.LbmError) as ei:
+        s.step(1)
+    assert ei.value.code == -5
+
+
+def test_invalid_inputs_rejected(gpu_lib):
+    say("invalid inputs")
+    with pytest.raises(gpu_lib.LbmError):
+        gpu_lib.Simulation(2, (16, 16), 0.5)
+    s = gpu_lib.Simulation(2, (32, 32), 0.7, max_particles=2)
+    with pytest.raises(gpu_lib.LbmError):  # overlap of more than half a radius
+        s.set_particles([[10, 10, 0], [12, 10, 0]], radius=[3, 3], rho_s=[1, 1])
+    with pytest.raises(gpu_lib.LbmError):  # more particles than reserved
+        s.set_particles(np.zeros((3, 3)) + 5, radius=[1, 1, 1], rho_s=[1, 1, 1])
+    with pytest.raises(gpu_lib.LbmError):  # wider than the periodic box
+        s.set_particles([[10, 10, 0]], radius=[20], rho_s=[1])
+
+
+# ---------------------------------------------- full-size workloads, 1-2 steps
+@pytest.mark.parametrize("name,steps", [("C2", 2), ("C3", 2)])
+def test_full_size_first_steps(gpu_lib, name, steps):
+    """The full C2 / C3 workloads (in the benchmark's launch configuration)
+    from the seeded initial state, a few steps, every field compared."""
+    w = I.workload(name)
+    parts = w.particles()
+    say("full size", name, w.shape, w.count, "particles", steps, "steps")
+    orc, gpu = make_pair(gpu_lib, w.dim, w.shape, w.tau, wall_y=w.wall_y,
+                         fluid_force=w.fluid_force, particle_accel=w.particle_accel,
+                         samples=w.samples, kn=w.kn, restitution=w.restitution, particles=parts)
+    orc.step(steps)
+    gpu.step(steps)
+    errs = compare(orc, gpu, with_f=(name == "C2"))
+    assert_close(errs, label=name)
+    # mass is conserved to rounding at full size
+    rho, _ = gpu.macro()
+    assert abs(rho.sum() - w.nodes) / w.nodes < 1e-13

@@ -1,0 +1,75 @@
+"""Storage-precision variants against the FP64 oracle.
+
+FP32-shifted storage (g_i = f_i - w_i in binary32, binary32 arithmetic) must
+keep the mean relative drag error, averaged over particles and over the last
+100 steps, within 1e-3 of FP64.  FP16 storage (g_i / w_i in binary16) has no
+target; its errors are reported.  Particle-side arithmetic is binary64 in all
+modes.
+"""
+import numpy as np
+import pytest
+
+from paper_1011_2613_amd import inputs as I
+from tests.parity_util import make_pair, rel_err
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def drag_errors(orc, gpu, steps, window):
+    orc.step(steps - window)
+    gpu.step(steps - window)
+    errs = []
+    for _ in range(window):
+        orc.step(1)
+        gpu.step(1)
+        F0, _ = orc.forces()
+        F1, _ = gpu.forces()
+        n0 = np.linalg.norm(F0, axis=1)
+        errs.append(np.linalg.norm(F1 - F0, axis=1) / n0)
+    errs = np.array(errs)
+    _, u0 = orc.macro()
+    _, u1 = gpu.macro()
+    return float(errs.mean()), float(errs.max()), rel_err(u1, u0)
+
+
+@pytest.mark.parametrize("storage,bound", [("fp32s", 1e-3), ("fp16s", 0.5)])
+def test_c1_drag_error(gpu_lib, storage, bound):
+    w = I.workload("C1")
+    parts = w.particles()
+    say("C1", storage)
+    orc, gpu = make_pair(gpu_lib, 2, w.shape, w.tau, fluid_force=w.fluid_force, samples=w.samples,
+                         kn=w.kn, restitution=w.restitution, particles=parts, storage=storage)
+    mean, mx, uerr = drag_errors(orc, gpu, w.steps, 100)
+    say("C1 %s: mean drag err %.3e, max %.3e, velocity err %.3e" % (storage, mean, mx, uerr))
+    assert mean <= bound
+
+
+@pytest.mark.parametrize("storage,bound", [("fp32s", 1e-3), ("fp16s", 0.5)])
+def test_d3q19_sedimenting_drag_error(gpu_lib, storage, bound):
+    box = (40, 48, 32)
+    n = 10
+    R = 4.0
+    pos = I.place_particles(3, box, R, n, 71, wall_y=True)
+    vel = I.random_velocities(3, n, 5e-3, 72)
+    parts = (pos, vel, np.zeros((n, 3)), np.full(n, R), np.full(n, 20.0), np.zeros(n, np.uint8))
+    say("D3Q19 sedimenting", storage)
+    orc, gpu = make_pair(gpu_lib, 3, box, 0.6, wall_y=True, particle_accel=(0, -2e-5, 0),
+                         samples=4, kn=2000.0, restitution=0.9, particles=parts, storage=storage)
+    mean, mx, uerr = drag_errors(orc, gpu, 400, 100)
+    say("D3Q19 %s: mean drag err %.3e, max %.3e, velocity err %.3e" % (storage, mean, mx, uerr))
+    assert mean <= bound
+
+
+def test_shifted_rest_state_is_exact(gpu_lib):
+    """In shifted storage the fluid at rest is g = 0 exactly and stays so."""
+    sim = gpu_lib.Simulation(3, (24, 20, 16), 0.7, storage="fp32s", wall_y=True, samples=4,
+                             kn=10.0, max_particles=2)
+    sim.set_particles([[6.0, 8.0, 8.0], [17.0, 10.0, 8.0]], radius=[3.0, 3.0], rho_s=[2.0, 2.0])
+    sim.step(20)
+    _, u = sim.macro()
+    F, _ = sim.forces()
+    assert np.all(u == 0.0) and np.all(F == 0.0)
