@@ -1,0 +1,70 @@
+/*
+ * mlp_closure.h -- C ABI of the learned drag closure in liblbimb.so.
+ *
+ * A multilayer perceptron 40 -> 128 -> 128 -> 128 -> 1 with SiLU on the hidden
+ * layers maps per-particle features (local solid fraction, particle Reynolds
+ * number, slip velocity, neighbour histogram) to a normalised drag.  Matrix
+ * products run on gfx950 matrix cores with bfloat16 operands and binary32
+ * accumulation; binary32 master weights are trained with Adam on the mean
+ * squared error.  Resolved LB-IMB drag (lbimb.h) is the training data and the
+ * judge; callers fall back to it outside the training envelope.
+ *
+ * Parameter vector (binary32, MLP_NPARAMS = 38401 values), in this order:
+ *   W1[128][40], b1[128], W2[128][128], b2[128], W3[128][128], b3[128],
+ *   W4[1][128], b4[1]         (row-major, output index first).
+ *
+ * Conventions: return 0 or a negative LBM_E_* code from lbimb.h; X, y and
+ * outputs are device pointers on the context's GPU unless ptr_kind says
+ * LBM_HOST; calls are ordered on the context's stream.  The caller owns the
+ * workspace and all buffers.
+ */
+#ifndef MLP_CLOSURE_H
+#define MLP_CLOSURE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MLP_NIN 40
+#define MLP_NHID 128
+#define MLP_NPARAMS 38401
+
+typedef struct mlp_ctx mlp_ctx;
+
+/* Device bytes for a context that trains on minibatches of up to
+ * `max_batch` rows (inference takes any number of rows). */
+int mlp_workspace_bytes(int64_t max_batch, size_t *bytes);
+
+int mlp_create(int64_t max_batch, void *workspace, size_t ws_bytes, void *hip_stream,
+               mlp_ctx **out);
+void mlp_destroy(mlp_ctx *ctx);
+
+/* Set / get the binary32 master parameters (layout above).  Setting also
+ * resets the Adam moments and step count. */
+int mlp_set_params(mlp_ctx *ctx, const float *params, int ptr_kind);
+int mlp_get_params(mlp_ctx *ctx, float *params, int ptr_kind);
+
+/* Inference: y[n] = MLP(X[n][40]) with the current parameters (device
+ * pointers, asynchronous on the context's stream). */
+int mlp_forward(mlp_ctx *ctx, const float *X, int64_t n, float *y);
+
+/* Gradient of the mean squared error (1/n) sum (MLP(X) - y)^2 with respect to
+ * every parameter, without updating them; grads[MLP_NPARAMS] and *loss are
+ * written (device pointers for X, y; grads and loss follow ptr_kind). */
+int mlp_gradients(mlp_ctx *ctx, const float *X, const float *y, int64_t n, float *grads,
+                  float *loss, int ptr_kind);
+
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8, learning rate lr) on the
+ * minibatch X[n][40], y[n], n <= max_batch.  *loss (host) receives the
+ * minibatch loss before the update when loss is not NULL. */
+int mlp_train_step(mlp_ctx *ctx, const float *X, const float *y, int64_t n, float lr,
+                   float *loss);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MLP_CLOSURE_H */

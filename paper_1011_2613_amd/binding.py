@@ -44,7 +44,9 @@ _SYMBOLS = ("lbm_workspace_bytes", "lbm_create", "lbm_destroy", "lbm_set_particl
             "lbm_set_distributions", "lbm_get_distributions", "lbm_step", "lbm_get_forces",
             "lbm_get_contact_forces", "lbm_get_particles", "lbm_get_macro", "lbm_get_q",
             "lbm_time", "lbm_particle_count", "lbm_set_timing", "lbm_get_timing", "lbm_save", "lbm_load",
-            "lbm_error_string", "lbm_last_error")
+            "lbm_error_string", "lbm_last_error",
+            "mlp_workspace_bytes", "mlp_create", "mlp_destroy", "mlp_set_params", "mlp_get_params",
+            "mlp_forward", "mlp_gradients", "mlp_train_step")
 
 
 def load():
@@ -87,8 +89,8 @@ def load():
     L.lbm_last_error.argtypes = [vp]
     L.lbm_last_error.restype = C.c_char_p
     for name in _SYMBOLS:
-        if name not in ("lbm_destroy", "lbm_time", "lbm_particle_count", "lbm_error_string",
-                        "lbm_last_error"):
+        if name.startswith("lbm_") and name not in ("lbm_destroy", "lbm_time", "lbm_particle_count",
+                                                    "lbm_error_string", "lbm_last_error"):
             getattr(L, name).restype = C.c_int
     _lib = L
     return L
@@ -278,3 +280,132 @@ def simulation_for(workload, storage="fp64", device="cuda:0", with_particles=Tru
         pos, vel, om, rad, rho, fixed = w.particles()
         sim.set_particles(pos, vel, om, rad, rho, fixed)
     return sim
+
+
+# ------------------------------------------------------------ drag closure
+MLP_NIN, MLP_NPARAMS = 40, 38401
+
+
+def _load_mlp(L):
+    if getattr(L, "_mlp_ready", False):
+        return L
+    vp, i64 = C.c_void_p, C.c_int64
+    L.mlp_workspace_bytes.argtypes = [i64, C.POINTER(C.c_size_t)]
+    L.mlp_create.argtypes = [i64, vp, C.c_size_t, vp, C.POINTER(vp)]
+    L.mlp_destroy.argtypes = [vp]
+    L.mlp_destroy.restype = None
+    L.mlp_set_params.argtypes = [vp, vp, C.c_int]
+    L.mlp_get_params.argtypes = [vp, vp, C.c_int]
+    L.mlp_forward.argtypes = [vp, vp, i64, vp]
+    L.mlp_gradients.argtypes = [vp, vp, vp, i64, vp, vp, C.c_int]
+    L.mlp_train_step.argtypes = [vp, vp, vp, i64, C.c_float, vp]
+    for n in ("mlp_workspace_bytes", "mlp_create", "mlp_set_params", "mlp_get_params", "mlp_forward",
+              "mlp_gradients", "mlp_train_step"):
+        getattr(L, n).restype = C.c_int
+    L._mlp_ready = True
+    return L
+
+
+class Mlp:
+    """The drag-closure MLP on one GPU (include/mlp_closure.h).  Inputs and
+    outputs are torch tensors on the context's device (binary32)."""
+
+    def __init__(self, max_batch=4096, device="cuda:0"):
+        import torch
+        self._torch = torch
+        L = _load_mlp(load())
+        nbytes = C.c_size_t(0)
+        rc = L.mlp_workspace_bytes(int(max_batch), C.byref(nbytes))
+        if rc:
+            raise LbmError(rc, "mlp_workspace_bytes")
+        self.device = torch.device(device)
+        self.max_batch = int(max_batch)
+        self.workspace = torch.empty(int(nbytes.value) + 256, dtype=torch.uint8, device=self.device)
+        aligned = (self.workspace.data_ptr() + 255) // 256 * 256
+        self.stream = torch.cuda.Stream(device=self.device)
+        h = C.c_void_p()
+        rc = L.mlp_create(int(max_batch), C.c_void_p(aligned), nbytes, C.c_void_p(self.stream.cuda_stream),
+                          C.byref(h))
+        if rc:
+            raise LbmError(rc, "mlp_create")
+        self._ctx = h
+
+    def close(self):
+        if getattr(self, "_ctx", None):
+            load().mlp_destroy(self._ctx)
+            self._ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _sync_in(self):
+        self.stream.wait_stream(self._torch.cuda.current_stream(self.device))
+
+    def _sync_out(self):
+        self._torch.cuda.current_stream(self.device).wait_stream(self.stream)
+
+    def set_params(self, params):
+        p = np.ascontiguousarray(np.asarray(params, dtype=np.float32).reshape(MLP_NPARAMS))
+        rc = load().mlp_set_params(self._ctx, _ptr(p), LBM_HOST)
+        if rc:
+            raise LbmError(rc, "mlp_set_params")
+
+    def get_params(self):
+        p = np.empty(MLP_NPARAMS, dtype=np.float32)
+        rc = load().mlp_get_params(self._ctx, _ptr(p), LBM_HOST)
+        if rc:
+            raise LbmError(rc, "mlp_get_params")
+        return p
+
+    def _dev(self, a, shape):
+        t = self._torch.as_tensor(a, dtype=self._torch.float32, device=self.device)
+        return t.reshape(shape).contiguous()
+
+    def forward(self, X):
+        X = self._dev(X, (-1, MLP_NIN))
+        y = self._torch.empty(X.shape[0], dtype=self._torch.float32, device=self.device)
+        self._sync_in()
+        rc = load().mlp_forward(self._ctx, _ptr(X), X.shape[0], _ptr(y))
+        if rc:
+            raise LbmError(rc, "mlp_forward")
+        self._sync_out()
+        return y
+
+    def gradients(self, X, y):
+        X = self._dev(X, (-1, MLP_NIN))
+        y = self._dev(y, (-1,))
+        g = np.empty(MLP_NPARAMS, dtype=np.float32)
+        loss = np.empty(1, dtype=np.float32)
+        self._sync_in()
+        rc = load().mlp_gradients(self._ctx, _ptr(X), _ptr(y), X.shape[0], _ptr(g), _ptr(loss), LBM_HOST)
+        if rc:
+            raise LbmError(rc, "mlp_gradients")
+        return g, float(loss[0])
+
+    def train_step(self, X, y, lr):
+        X = self._dev(X, (-1, MLP_NIN))
+        y = self._dev(y, (-1,))
+        loss = np.empty(1, dtype=np.float32)
+        self._sync_in()
+        rc = load().mlp_train_step(self._ctx, _ptr(X), _ptr(y), X.shape[0], C.c_float(lr), _ptr(loss))
+        if rc:
+            raise LbmError(rc, "mlp_train_step")
+        return float(loss[0])
+
+
+def mlp_unpack(p):
+    """Packed parameter vector -> [[W1, b1], ..., [W4, b4]] (views)."""
+    p = np.asarray(p)
+    out, o = [], 0
+    for fin, fout in ((40, 128), (128, 128), (128, 128), (128, 1)):
+        W = p[o:o + fin * fout].reshape(fout, fin); o += fin * fout
+        b = p[o:o + fout]; o += fout
+        out.append([W, b])
+    return out
+
+
+def mlp_pack(params):
+    return np.concatenate([np.concatenate([np.asarray(W).ravel(), np.asarray(b).ravel()]) for W, b in params])

@@ -73,6 +73,7 @@ struct LBArgs {
     const double *beta_tab;   // beta(eps) for count 0..Smax
     const double *arel_tab;   // (1 - beta) / tau for count 0..Smax
     double *q;             // [D][N] IMB momentum exchange
+    int *ctot;             // [N] total sub-sample count at covered nodes
     const double *px, *pv, *pw;  // particle SoA
     int np;
     Geom g;
@@ -97,8 +98,7 @@ struct FootArgs {
 struct ForceArgs {
     Particles P;
     Geom g;
-    const uint8_t *nown;
-    const uint32_t *slots;
+    const int *ctot;
     const double *q;
     int S;
     int D;

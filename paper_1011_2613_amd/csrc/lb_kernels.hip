@@ -126,12 +126,31 @@ __device__ __forceinline__ R cmoment(const R (&v)[L::Q]) {
     return s;
 }
 
+// ------------------------------------------------------------- addressing
+// Every direction array has a base address that is uniform across the grid
+// (scalar registers); a node is a 32-bit byte offset from it when the array is
+// below 4 GiB, so loads and stores use the scalar-base + vector-offset form.
+template <class T, bool OFF32>
+__device__ __forceinline__ const T *at(const T *base, uint64_t idx) {
+    if (OFF32) return (const T *)((const char *)base + (uint32_t)((uint32_t)idx * (uint32_t)sizeof(T)));
+    return base + idx;
+}
+
+template <class T, bool OFF32>
+__device__ __forceinline__ T *at(T *base, uint64_t idx) {
+    if (OFF32) return (T *)((char *)base + (uint32_t)((uint32_t)idx * (uint32_t)sizeof(T)));
+    return base + idx;
+}
+
 // ------------------------------------------------------------- pull gather
-template <class L, class T>
+// f_i(x) = A_i(x - c_i), or A_opp(i)(x) when x - c_i lies beyond a wall.  All
+// threads of a block share y and z (the grid is one block row per lattice row),
+// so the bounce-back test and the direction base are uniform per block.
+template <class L, class T, bool OFF32>
 __device__ __forceinline__ void gather(const T *__restrict__ A, const Geom &g, int x, int y, int z,
-                                       int64_t n, T (&f)[L::Q]) {
+                                       uint64_t n, T (&f)[L::Q]) {
     const int nx = g.nx, ny = g.ny, nz = g.nz;
-    const int64_t N = g.N;
+    const uint64_t N = (uint64_t)g.N;
     const int xm = x == 0 ? nx - 1 : x - 1, xp = x == nx - 1 ? 0 : x + 1;
     int ym = y - 1, yp = y + 1;
     bool lo = false, hi = false;
@@ -149,79 +168,93 @@ __device__ __forceinline__ void gather(const T *__restrict__ A, const Geom &g, i
         const int sy = L::cy[i] == 0 ? y : (L::cy[i] > 0 ? ym : yp);
         const int sz = L::cz[i] == 0 ? z : (L::cz[i] > 0 ? zm : zp);
         const bool bb = (L::cy[i] > 0 && lo) || (L::cy[i] < 0 && hi);
-        const int64_t src = bb ? (int64_t)L::opp[i] * N + n
-                               : (int64_t)i * N + (int64_t)sx + (int64_t)nx * ((int64_t)sy + (int64_t)ny * sz);
-        f[i] = A[src];
+        const T *base = A + (uint64_t)(bb ? L::opp[i] : i) * N;
+        const uint64_t src = bb ? n : (uint64_t)sx + (uint64_t)nx * ((uint64_t)sy + (uint64_t)ny * (uint64_t)sz);
+        f[i] = *at<T, OFF32>(base, src);
     }
 }
 
 // ------------------------------------------------------ FP64 collision
+// Equilibria are evaluated where they are used and every post-collision value
+// is stored as soon as it is known, so only the Q gathered populations stay
+// live in registers.
 template <class L>
-__device__ __forceinline__ void collide_f64(const LBArgs &a, int64_t n, int x, int y, int z,
-                                            double (&f)[L::Q], int nown) {
+struct Eq64 {
+    double ux, uy, uz, t15, wr[3];
+    __device__ __forceinline__ double operator()(int i) const {
+        if (i == 0) return wr[0] * (1.0 - t15);
+        const double cu = cdot<L>(i, ux, uy, uz);
+        return wr[L::wc[i]] * (1.0 + 3.0 * cu + 4.5 * cu * cu - t15);
+    }
+};
+
+template <class L, bool OFF32>
+__device__ __forceinline__ void collide_f64(const LBArgs &a, uint64_t n, int x, int y, int z,
+                                            const double (&f)[L::Q], int nown) {
     double rho = f[0];
 #pragma unroll
     for (int i = 1; i < L::Q; i++) rho = rho + f[i];
     const double jx = cmoment<L, 0>(f), jy = cmoment<L, 1>(f);
     const double jz = L::D == 3 ? cmoment<L, 2>(f) : 0.0;
-    const double ux = jx / rho, uy = jy / rho, uz = L::D == 3 ? jz / rho : 0.0;
-    double usq = ux * ux + uy * uy;
-    if (L::D == 3) usq = usq + uz * uz;
-    const double t15 = 1.5 * usq;
-    const double wr[3] = {L::w[0] * rho, L::w[1] * rho, L::w[2] * rho};
+    Eq64<L> eq;
+    eq.ux = jx / rho;
+    eq.uy = jy / rho;
+    eq.uz = L::D == 3 ? jz / rho : 0.0;
+    double usq = eq.ux * eq.ux + eq.uy * eq.uy;
+    if (L::D == 3) usq = usq + eq.uz * eq.uz;
+    eq.t15 = 1.5 * usq;
+    eq.wr[0] = L::w[0] * rho;
+    eq.wr[1] = L::w[1] * rho;
+    eq.wr[2] = L::w[2] * rho;
     const double w3r[3] = {3.0 * L::w[0] * rho, 3.0 * L::w[1] * rho, 3.0 * L::w[2] * rho};
+    double *B = (double *)a.B;
+    const uint64_t N = (uint64_t)a.g.N;
 
-    double feq[L::Q];
-#pragma unroll
-    for (int i = 0; i < L::Q; i++) {
-        if (i == 0) {
-            feq[i] = wr[0] * (1.0 - t15);
-        } else {
-            const double cu = cdot<L>(i, ux, uy, uz);
-            feq[i] = wr[L::wc[i]] * (1.0 + 3.0 * cu + 4.5 * cu * cu - t15);
-        }
-    }
-
-    double out[L::Q];
-    if (nown == 0) {
+    // A wavefront with no covered node takes the plain BGK path.  Otherwise
+    // every lane takes the IMB path; an uncovered lane then has beta = 0,
+    // a = 1/tau and V_S = 0, for which the IMB formula gives the same bits as
+    // the plain one (beta * Omega adds +-0).  Keeping the wavefront converged
+    // keeps every population store a full-wavefront store.
+    if (!__any(nown != 0)) {
         const double ar = a.arel0;
 #pragma unroll
-        for (int i = 0; i < L::Q; i++)
-            out[i] = f[i] - ar * (f[i] - feq[i]) + w3r[L::wc[i]] * a.cg[i];
-    } else {
-        if (nown > MAX_OWNERS) atomicOr(a.flags, FLAG_SLOT_OVERFLOW);
-        double V[3];
-        const int total = solid_velocity<L>(a, n, nown, x, y, z, V);
-        const int cc = total < a.Smax ? total : a.Smax;
-        const double beta = a.beta_tab[cc];
-        const double ar = a.arel_tab[cc];
-        double VV = V[0] * V[0] + V[1] * V[1];
-        if (L::D == 3) VV = VV + V[2] * V[2];
-        const double v15 = 1.5 * VV;
-        double Om[L::Q];
-#pragma unroll
         for (int i = 0; i < L::Q; i++) {
-            double feqV;
-            if (i == 0) {
-                feqV = wr[0] * (1.0 - v15);
-            } else {
-                const double cV = cdot<L>(i, V[0], V[1], V[2]);
-                feqV = wr[L::wc[i]] * (1.0 + 3.0 * cV + 4.5 * cV * cV - v15);
-            }
-            const int o = L::opp[i];
-            Om[i] = (f[o] - f[i]) + (feqV - feq[o]);
+            const double out = f[i] - ar * (f[i] - eq(i)) + w3r[L::wc[i]] * a.cg[i];
+            __builtin_nontemporal_store(out, at<double, OFF32>(B + (uint64_t)i * N, n));
         }
-#pragma unroll
-        for (int i = 0; i < L::Q; i++)
-            out[i] = f[i] - ar * (f[i] - feq[i]) + beta * Om[i] + w3r[L::wc[i]] * a.cg[i];
-        const int64_t N = a.g.N;
-        a.q[n] = beta * cmoment<L, 0>(Om);
-        a.q[N + n] = beta * cmoment<L, 1>(Om);
-        if (L::D == 3) a.q[2 * N + n] = beta * cmoment<L, 2>(Om);
+        return;
     }
-    double *B = (double *)a.B;
+    if (nown > MAX_OWNERS) atomicOr(a.flags, FLAG_SLOT_OVERFLOW);
+    double V[3] = {0.0, 0.0, 0.0};
+    int total = 0;
+    if (nown != 0) total = solid_velocity<L>(a, (int64_t)n, nown, x, y, z, V);
+    const int cc = total < a.Smax ? total : a.Smax;
+    const double beta = nown != 0 ? a.beta_tab[cc] : 0.0;
+    const double ar = nown != 0 ? a.arel_tab[cc] : a.arel0;
+    double VV = V[0] * V[0] + V[1] * V[1];
+    if (L::D == 3) VV = VV + V[2] * V[2];
+    Eq64<L> eqV = eq;
+    eqV.ux = V[0];
+    eqV.uy = V[1];
+    eqV.uz = V[2];
+    eqV.t15 = 1.5 * VV;
+    double mx = 0.0, my = 0.0, mz = 0.0;
 #pragma unroll
-    for (int i = 0; i < L::Q; i++) __builtin_nontemporal_store(out[i], &B[(int64_t)i * a.g.N + n]);
+    for (int i = 0; i < L::Q; i++) {
+        const int o = L::opp[i];
+        const double Om = (f[o] - f[i]) + (eqV(i) - eq(o));
+        const double out = f[i] - ar * (f[i] - eq(i)) + beta * Om + w3r[L::wc[i]] * a.cg[i];
+        __builtin_nontemporal_store(out, at<double, OFF32>(B + (uint64_t)i * N, n));
+        if (L::cx[i] > 0) mx = mx + Om; else if (L::cx[i] < 0) mx = mx - Om;
+        if (L::cy[i] > 0) my = my + Om; else if (L::cy[i] < 0) my = my - Om;
+        if (L::D == 3) { if (L::cz[i] > 0) mz = mz + Om; else if (L::cz[i] < 0) mz = mz - Om; }
+    }
+    if (nown != 0) {
+        a.q[n] = beta * mx;
+        a.q[N + n] = beta * my;
+        if (L::D == 3) a.q[2 * N + n] = beta * mz;
+        a.ctot[n] = total;
+    }
 }
 
 // ------------------------------------------- shifted storage, FP32 compute
@@ -229,9 +262,9 @@ __device__ __forceinline__ void collide_f64(const LBArgs &a, int64_t n, int x, i
 // g^eq_i = w_i (drho + rho (3 cu + 4.5 cu^2 - 1.5 u^2)); the solid operator
 // keeps its exact form because the w_i terms cancel:
 // Omega_i = (g_-i - g_i) + w_i rho [(3 cV + 4.5 cV^2 - 1.5 V^2) - (-3 cu + 4.5 cu^2 - 1.5 u^2)].
-template <class L, int ST>
-__device__ __forceinline__ void collide_shifted(const LBArgs &a, int64_t n, int x, int y, int z,
-                                                float (&gg)[L::Q], int nown) {
+template <class L, int ST, bool OFF32>
+__device__ __forceinline__ void collide_shifted(const LBArgs &a, uint64_t n, int x, int y, int z,
+                                                const float (&gg)[L::Q], int nown) {
     float drho = gg[0];
 #pragma unroll
     for (int i = 1; i < L::Q; i++) drho = drho + gg[i];
@@ -243,81 +276,83 @@ __device__ __forceinline__ void collide_shifted(const LBArgs &a, int64_t n, int 
     if (L::D == 3) usq = usq + uz * uz;
     const float t15 = 1.5f * usq;
     const float wf[3] = {(float)L::w[0], (float)L::w[1], (float)L::w[2]};
-
-    float geq[L::Q], cus[L::Q];
-#pragma unroll
-    for (int i = 0; i < L::Q; i++) {
-        const float cu = i == 0 ? 0.0f : cdot<L>(i, ux, uy, uz);
-        cus[i] = cu;
-        geq[i] = wf[L::wc[i]] * (drho + rho * (3.0f * cu + 4.5f * cu * cu - t15));
-    }
-    float out[L::Q];
-    if (nown == 0) {
-        const float ar = a.arel0f;
-#pragma unroll
-        for (int i = 0; i < L::Q; i++)
-            out[i] = gg[i] - ar * (gg[i] - geq[i]) + (3.0f * wf[L::wc[i]] * rho) * a.cgf[i];
-    } else {
-        if (nown > MAX_OWNERS) atomicOr(a.flags, FLAG_SLOT_OVERFLOW);
-        double Vd[3];
-        const int total = solid_velocity<L>(a, n, nown, x, y, z, Vd);
-        const int cc = total < a.Smax ? total : a.Smax;
-        const float beta = (float)a.beta_tab[cc];
-        const float ar = (float)a.arel_tab[cc];
-        const float V0 = (float)Vd[0], V1 = (float)Vd[1], V2 = (float)Vd[2];
-        float VV = V0 * V0 + V1 * V1;
-        if (L::D == 3) VV = VV + V2 * V2;
-        const float v15 = 1.5f * VV;
-        float Om[L::Q];
-#pragma unroll
-        for (int i = 0; i < L::Q; i++) {
-            const float cV = i == 0 ? 0.0f : cdot<L>(i, V0, V1, V2);
-            const float cu = cus[i];
-            const float pV = 3.0f * cV + 4.5f * cV * cV - v15;
-            const float pu = -3.0f * cu + 4.5f * cu * cu - t15;
-            Om[i] = (gg[L::opp[i]] - gg[i]) + (wf[L::wc[i]] * rho) * (pV - pu);
-        }
-#pragma unroll
-        for (int i = 0; i < L::Q; i++)
-            out[i] = gg[i] - ar * (gg[i] - geq[i]) + beta * Om[i] + (3.0f * wf[L::wc[i]] * rho) * a.cgf[i];
-        const int64_t N = a.g.N;
-        a.q[n] = (double)(beta * cmoment<L, 0>(Om));
-        a.q[N + n] = (double)(beta * cmoment<L, 1>(Om));
-        if (L::D == 3) a.q[2 * N + n] = (double)(beta * cmoment<L, 2>(Om));
-    }
+    const float wrf[3] = {wf[0] * rho, wf[1] * rho, wf[2] * rho};
+    const float w3r[3] = {3.0f * wf[0] * rho, 3.0f * wf[1] * rho, 3.0f * wf[2] * rho};
     using T = typename Store<ST>::T;
     T *B = (T *)a.B;
+    const uint64_t N = (uint64_t)a.g.N;
+    auto cu_of = [&](int i) { return i == 0 ? 0.0f : cdot<L>(i, ux, uy, uz); };
+    auto put = [&](int i, float v) {
+        T s;
+        if (ST == 1) s = (T)v;
+        else s = (T)(v * L::invw[L::wc[i]]);
+        __builtin_nontemporal_store(s, at<T, OFF32>(B + (uint64_t)i * N, n));
+    };
+    if (!__any(nown != 0)) {
+        const float ar = a.arel0f;
+#pragma unroll
+        for (int i = 0; i < L::Q; i++) {
+            const float cu = cu_of(i);
+            const float geq = wf[L::wc[i]] * (drho + rho * (3.0f * cu + 4.5f * cu * cu - t15));
+            put(i, gg[i] - ar * (gg[i] - geq) + w3r[L::wc[i]] * a.cgf[i]);
+        }
+        return;
+    }
+    if (nown > MAX_OWNERS) atomicOr(a.flags, FLAG_SLOT_OVERFLOW);
+    double Vd[3] = {0.0, 0.0, 0.0};
+    int total = 0;
+    if (nown != 0) total = solid_velocity<L>(a, (int64_t)n, nown, x, y, z, Vd);
+    const int cc = total < a.Smax ? total : a.Smax;
+    const float beta = nown != 0 ? (float)a.beta_tab[cc] : 0.0f;
+    const float ar = nown != 0 ? (float)a.arel_tab[cc] : a.arel0f;
+    const float V0 = (float)Vd[0], V1 = (float)Vd[1], V2 = (float)Vd[2];
+    float VV = V0 * V0 + V1 * V1;
+    if (L::D == 3) VV = VV + V2 * V2;
+    const float v15 = 1.5f * VV;
+    float mx = 0.0f, my = 0.0f, mz = 0.0f;
 #pragma unroll
     for (int i = 0; i < L::Q; i++) {
-        T v;
-        if (ST == 1) v = (T)out[i];
-        else v = (T)(out[i] * L::invw[L::wc[i]]);
-        __builtin_nontemporal_store(v, &B[(int64_t)i * a.g.N + n]);
+        const float cV = i == 0 ? 0.0f : cdot<L>(i, V0, V1, V2);
+        const float cu = cu_of(i);
+        const float pV = 3.0f * cV + 4.5f * cV * cV - v15;
+        const float pu = -3.0f * cu + 4.5f * cu * cu - t15;
+        const float Om = (gg[L::opp[i]] - gg[i]) + wrf[L::wc[i]] * (pV - pu);
+        const float geq = wf[L::wc[i]] * (drho + rho * (3.0f * cu + 4.5f * cu * cu - t15));
+        put(i, gg[i] - ar * (gg[i] - geq) + beta * Om + w3r[L::wc[i]] * a.cgf[i]);
+        if (L::cx[i] > 0) mx = mx + Om; else if (L::cx[i] < 0) mx = mx - Om;
+        if (L::cy[i] > 0) my = my + Om; else if (L::cy[i] < 0) my = my - Om;
+        if (L::D == 3) { if (L::cz[i] > 0) mz = mz + Om; else if (L::cz[i] < 0) mz = mz - Om; }
+    }
+    if (nown != 0) {
+        a.q[n] = (double)(beta * mx);
+        a.q[N + n] = (double)(beta * my);
+        if (L::D == 3) a.q[2 * N + n] = (double)(beta * mz);
+        a.ctot[n] = total;
     }
 }
 
-template <class L, int ST>
+template <class L, int ST, bool OFF32>
 __global__ __launch_bounds__(256) void k_lb(LBArgs a) {
     const int x = blockIdx.x * blockDim.x + threadIdx.x;
     if (x >= a.g.nx) return;
     const int y = blockIdx.y, z = blockIdx.z;
-    const int64_t n = (int64_t)x + (int64_t)a.g.nx * ((int64_t)y + (int64_t)a.g.ny * z);
+    const uint64_t n = (uint64_t)x + (uint64_t)a.g.nx * ((uint64_t)y + (uint64_t)a.g.ny * (uint64_t)z);
     using T = typename Store<ST>::T;
     T f[L::Q];
-    gather<L, T>((const T *)a.A, a.g, x, y, z, n, f);
+    gather<L, T, OFF32>((const T *)a.A, a.g, x, y, z, n, f);
     const int nown = a.nown[n];
     if (ST == 0) {
         double fd[L::Q];
 #pragma unroll
         for (int i = 0; i < L::Q; i++) fd[i] = (double)f[i];
-        collide_f64<L>(a, n, x, y, z, fd, nown);
+        collide_f64<L, OFF32>(a, n, x, y, z, fd, nown);
     } else {
         float gg[L::Q];
         const float wf[3] = {(float)L::w[0], (float)L::w[1], (float)L::w[2]};
 #pragma unroll
         for (int i = 0; i < L::Q; i++)
             gg[i] = ST == 1 ? (float)f[i] : wf[L::wc[i]] * (float)f[i];
-        collide_shifted<L, ST>(a, n, x, y, z, gg, nown);
+        collide_shifted<L, ST, OFF32>(a, n, x, y, z, gg, nown);
     }
 }
 
@@ -348,7 +383,7 @@ __global__ void k_get_f(Geom g, const void *A, double *f) {
     const int64_t n = (int64_t)x + (int64_t)g.nx * ((int64_t)y + (int64_t)g.ny * z);
     using T = typename Store<ST>::T;
     T v[L::Q];
-    gather<L, T>((const T *)A, g, x, y, z, n, v);
+    gather<L, T, false>((const T *)A, g, x, y, z, (uint64_t)n, v);
 #pragma unroll
     for (int i = 0; i < L::Q; i++) f[(int64_t)i * g.N + n] = decode<L, ST>(i, v[i]);
 }
@@ -361,7 +396,7 @@ __global__ void k_macro(Geom g, const void *A, double *rho, double *u) {
     const int64_t n = (int64_t)x + (int64_t)g.nx * ((int64_t)y + (int64_t)g.ny * z);
     using T = typename Store<ST>::T;
     T v[L::Q];
-    gather<L, T>((const T *)A, g, x, y, z, n, v);
+    gather<L, T, false>((const T *)A, g, x, y, z, (uint64_t)n, v);
     double fd[L::Q];
 #pragma unroll
     for (int i = 0; i < L::Q; i++) fd[i] = decode<L, ST>(i, v[i]);
@@ -421,7 +456,9 @@ template <class L, int ST>
 static hipError_t lb_dispatch(const LBArgs &a, hipStream_t s) {
     int block;
     dim3 grid = lattice_grid(a.g, block);
-    hipLaunchKernelGGL((k_lb<L, ST>), grid, dim3(block), 0, s, a);
+    const uint64_t bytes = (uint64_t)a.g.N * sizeof(typename Store<ST>::T);
+    if (bytes < ((uint64_t)1 << 32)) hipLaunchKernelGGL((k_lb<L, ST, true>), grid, dim3(block), 0, s, a);
+    else hipLaunchKernelGGL((k_lb<L, ST, false>), grid, dim3(block), 0, s, a);
     return hipGetLastError();
 }
 

@@ -74,17 +74,70 @@ __global__ __launch_bounds__(256) void k_foot_clear(FootArgs a) {
     }
 }
 
-// Paint the particle's footprint: count of sub-cell samples inside the
-// particle per node (sample offsets (k + 1/2)/S - 1/2 per axis, inside test
-// dx^2 + dy^2 (+ dz^2) <= R^2 evaluated left to right), then claim an owner
-// slot on every covered node.  The squared offsets are separable, so each
-// node needs S^D additions; nodes whose nearest sample is outside or whose
-// farthest sample is inside are decided from per-axis extremes, exactly,
-// because rounded addition is monotone.
-__global__ __launch_bounds__(256) void k_foot_paint(FootArgs a, int D) {
+// Number of sub-cell samples of a node inside a particle: offsets
+// (k + 1/2)/S - 1/2 per axis from the node, inside test dx^2 + dy^2 (+ dz^2)
+// <= R^2 evaluated left to right, d0/d1/d2 the node-minus-centre displacement.
+// The squared offsets are separable, so a node needs S^D additions; nodes whose
+// nearest sample is outside or whose farthest sample is inside are decided
+// from per-axis extremes, exactly, because rounded addition is monotone.
+template <int D, int S>
+__device__ __forceinline__ int sample_count(double d0, double d1, double d2, double R2) {
+    double sx[S], sy[S], sz[S];
+    double mnx = 1e300, mxx = -1.0, mny = 1e300, mxy = -1.0, mnz = 1e300, mxz = -1.0;
+#pragma unroll
+    for (int s = 0; s < S; s++) {
+        const double off = ((double)s + 0.5) / (double)S - 0.5;
+        const double ex = d0 + off, ey = d1 + off;
+        sx[s] = ex * ex;
+        sy[s] = ey * ey;
+        mnx = fmin(mnx, sx[s]); mxx = fmax(mxx, sx[s]);
+        mny = fmin(mny, sy[s]); mxy = fmax(mxy, sy[s]);
+        if (D == 3) {
+            const double ez = d2 + off;
+            sz[s] = ez * ez;
+            mnz = fmin(mnz, sz[s]); mxz = fmax(mxz, sz[s]);
+        } else {
+            sz[s] = 0.0;
+        }
+    }
+    int count = 0;
+    if (D == 2) {
+        if (mnx + mny > R2) return 0;
+        if (mxx + mxy <= R2) return S * S;
+#pragma unroll
+        for (int ky = 0; ky < S; ky++)
+#pragma unroll
+            for (int kx = 0; kx < S; kx++) count += (sx[kx] + sy[ky] <= R2) ? 1 : 0;
+    } else {
+        if (mnx + mny + mnz > R2) return 0;
+        if (mxx + mxy + mxz <= R2) return S * S * S;
+#pragma unroll
+        for (int kz = 0; kz < S; kz++)
+#pragma unroll
+            for (int ky = 0; ky < S; ky++)
+#pragma unroll
+                for (int kx = 0; kx < S; kx++) count += (sx[kx] + sy[ky] + sz[kz] <= R2) ? 1 : 0;
+    }
+    return count;
+}
+
+// Node k of a bounding box with extents ext[] starting at lo[]; consecutive k
+// walk y first, then z, then x, so the lanes of a wavefront touch different
+// lattice rows (different words of the owner-count array).
+__device__ __forceinline__ void box_node(int k, const int lo[3], const int ext[3], int &cx, int &cy,
+                                         int &cz) {
+    cy = lo[1] + k % ext[1];
+    const int r = k / ext[1];
+    cz = lo[2] + r % ext[2];
+    cx = lo[0] + r / ext[2];
+}
+
+// Paint the particle's footprint: sample count per node of the bounding box,
+// then claim an owner slot on every covered node.
+template <int D, int S>
+__global__ __launch_bounds__(256) void k_foot_paint(FootArgs a) {
     const int p = blockIdx.x;
     const int P = a.P.np;
-    const int S = a.S;
     int lo[3], hi[3];
     bbox(a.P, p, D, lo, hi);
     if (threadIdx.x == 0)
@@ -92,58 +145,22 @@ __global__ __launch_bounds__(256) void k_foot_paint(FootArgs a, int D) {
             a.P.bb[d * P + p] = lo[d];
             a.P.bb[(3 + d) * P + p] = hi[d];
         }
-    const int ext0 = hi[0] - lo[0] + 1, ext1 = hi[1] - lo[1] + 1, ext2 = hi[2] - lo[2] + 1;
-    const int total = ext0 * ext1 * ext2;
+    const int ext[3] = {hi[0] - lo[0] + 1, hi[1] - lo[1] + 1, hi[2] - lo[2] + 1};
+    const int total = ext[0] * ext[1] * ext[2];
     const double r = a.P.R[p];
     const double R2 = r * r;
     const double xp0 = a.P.x[p], xp1 = a.P.x[P + p], xp2 = D == 3 ? a.P.x[2 * P + p] : 0.0;
     const int64_t N = a.g.N;
     for (int k = threadIdx.x; k < total; k += blockDim.x) {
-        const int cx = lo[0] + k % ext0;
-        const int cy = lo[1] + (k / ext0) % ext1;
-        const int cz = lo[2] + k / (ext0 * ext1);
+        int cx, cy, cz;
+        box_node(k, lo, ext, cx, cy, cz);
         const int ix = wrapc(a.g, 0, cx), iy = wrapc(a.g, 1, cy);
         const int iz = D == 3 ? wrapc(a.g, 2, cz) : 0;
         if (iy < 0) continue;
         const double d0 = ndisp(a.g, 0, ix, xp0);
         const double d1 = ndisp(a.g, 1, iy, xp1);
         const double d2 = D == 3 ? ndisp(a.g, 2, iz, xp2) : 0.0;
-        double sx[8], sy[8], sz[8];
-        double mnx = 1e300, mxx = -1.0, mny = 1e300, mxy = -1.0, mnz = 1e300, mxz = -1.0;
-        for (int s = 0; s < S; s++) {
-            const double off = ((double)s + 0.5) / (double)S - 0.5;
-            const double ex = d0 + off, ey = d1 + off;
-            sx[s] = ex * ex;
-            sy[s] = ey * ey;
-            mnx = fmin(mnx, sx[s]); mxx = fmax(mxx, sx[s]);
-            mny = fmin(mny, sy[s]); mxy = fmax(mxy, sy[s]);
-            if (D == 3) {
-                const double ez = d2 + off;
-                sz[s] = ez * ez;
-                mnz = fmin(mnz, sz[s]); mxz = fmax(mxz, sz[s]);
-            }
-        }
-        int count;
-        if (D == 2) {
-            if (mnx + mny > R2) count = 0;
-            else if (mxx + mxy <= R2) count = S * S;
-            else {
-                count = 0;
-                for (int ky = 0; ky < S; ky++)
-                    for (int kx = 0; kx < S; kx++) count += (sx[kx] + sy[ky] <= R2) ? 1 : 0;
-            }
-        } else {
-            if (mnx + mny + mnz > R2) count = 0;
-            else if (mxx + mxy + mxz <= R2) count = S * S * S;
-            else {
-                count = 0;
-                for (int kz = 0; kz < S; kz++)
-                    for (int ky = 0; ky < S; ky++) {
-                        const double sxy0 = sy[ky];
-                        for (int kx = 0; kx < S; kx++) count += (sx[kx] + sxy0 + sz[kz] <= R2) ? 1 : 0;
-                    }
-            }
-        }
+        const int count = sample_count<D, S>(d0, d1, d2, R2);
         if (count == 0) continue;
         const int64_t n = (int64_t)ix + (int64_t)a.g.nx * ((int64_t)iy + (int64_t)a.g.ny * iz);
         uint32_t *word = (uint32_t *)(a.nown + (n & ~(int64_t)3));
@@ -182,61 +199,83 @@ __device__ __forceinline__ double shfl_xor_d(double v, int m) {
     return __shfl_xor(v, m, 64);
 }
 
-// One wavefront per particle: lanes walk the particle's bounding box, add
-// s_pn q_n and r_pn x (s_pn q_n) into TwoSum accumulators, then the 64 lanes
-// merge their accumulators with butterfly shuffles.  F_p = -sum, T_p = -sum.
+// One workgroup per particle.  A thread takes four nodes of the bounding box
+// at a time, recomputes the particle's own sample count on each (the same
+// exact test as the paint kernel), and loads q_n and the node's total count
+// for all four before using them, so the loads of a batch are in flight
+// together.  s_pn q_n and r_pn x (s_pn q_n) go into TwoSum accumulators; each
+// wavefront merges its lanes with butterfly shuffles and the first thread
+// merges the wavefronts in a fixed order.  F_p = -sum, T_p = -sum.
+template <int D, int S>
 __global__ __launch_bounds__(256) void k_force(ForceArgs a) {
+    __shared__ double part[4][12];
+    constexpr int U = 4;
     const int lane = threadIdx.x & 63;
-    const int p = blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
+    const int wave = threadIdx.x >> 6;
+    const int nw = blockDim.x >> 6;
+    const int p = blockIdx.x;
     const int P = a.P.np;
-    if (p >= P) return;
-    const int D = a.D;
     int lo[3], ext[3];
     for (int d = 0; d < 3; d++) {
         lo[d] = a.P.bb[d * P + p];
         ext[d] = a.P.bb[(3 + d) * P + p] - lo[d] + 1;
     }
     const int total = ext[0] * ext[1] * ext[2];
+    const double r = a.P.R[p];
+    const double R2 = r * r;
     const double xp0 = a.P.x[p], xp1 = a.P.x[P + p], xp2 = D == 3 ? a.P.x[2 * P + p] : 0.0;
     const int64_t N = a.g.N;
     Acc F[3] = {{0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}};
     Acc T[3] = {{0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}};
-    for (int k = lane; k < total; k += 64) {
-        const int cx = lo[0] + k % ext[0];
-        const int cy = lo[1] + (k / ext[0]) % ext[1];
-        const int cz = lo[2] + k / (ext[0] * ext[1]);
-        const int ix = wrapc(a.g, 0, cx), iy = wrapc(a.g, 1, cy);
-        const int iz = D == 3 ? wrapc(a.g, 2, cz) : 0;
-        if (iy < 0) continue;
-        const int64_t n = (int64_t)ix + (int64_t)a.g.nx * ((int64_t)iy + (int64_t)a.g.ny * iz);
-        const int no = a.nown[n];
-        if (no == 0) continue;
-        const int kk = no < MAX_OWNERS ? no : MAX_OWNERS;
-        int cnt = 0, tot = 0;
-        for (int j = 0; j < kk; j++) {
-            const uint32_t r = a.slots[(int64_t)j * N + n];
-            const int c = (int)(r & ((1u << SLOT_COUNT_BITS) - 1u));
-            tot += c;
-            if ((int)(r >> SLOT_COUNT_BITS) == p) cnt = c;
+    for (int base = threadIdx.x; base < total; base += U * blockDim.x) {
+        int cnt[U];
+        int64_t nn[U];
+        double rr[U][3];
+#pragma unroll
+        for (int u = 0; u < U; u++) {
+            const int k = base + u * blockDim.x;
+            cnt[u] = 0;
+            nn[u] = 0;
+            rr[u][0] = rr[u][1] = rr[u][2] = 0.0;
+            if (k >= total) continue;
+            int cx, cy, cz;
+            box_node(k, lo, ext, cx, cy, cz);
+            const int ix = wrapc(a.g, 0, cx), iy = wrapc(a.g, 1, cy);
+            const int iz = D == 3 ? wrapc(a.g, 2, cz) : 0;
+            if (iy < 0) continue;
+            rr[u][0] = ndisp(a.g, 0, ix, xp0);
+            rr[u][1] = ndisp(a.g, 1, iy, xp1);
+            rr[u][2] = D == 3 ? ndisp(a.g, 2, iz, xp2) : 0.0;
+            cnt[u] = sample_count<D, S>(rr[u][0], rr[u][1], rr[u][2], R2);
+            if (cnt[u] > 0) nn[u] = (int64_t)ix + (int64_t)a.g.nx * ((int64_t)iy + (int64_t)a.g.ny * iz);
         }
-        if (cnt == 0) continue;
-        const double sh = (double)cnt / (double)tot;
-        double t[3];
-        t[0] = sh * a.q[n];
-        t[1] = sh * a.q[N + n];
-        t[2] = D == 3 ? sh * a.q[2 * N + n] : 0.0;
-        const double rx = ndisp(a.g, 0, ix, xp0);
-        const double ry = ndisp(a.g, 1, iy, xp1);
-        acc_add(F[0], t[0]);
-        acc_add(F[1], t[1]);
-        if (D == 3) {
-            const double rz = ndisp(a.g, 2, iz, xp2);
-            acc_add(F[2], t[2]);
-            acc_add(T[0], ry * t[2] - rz * t[1]);
-            acc_add(T[1], rz * t[0] - rx * t[2]);
-            acc_add(T[2], rx * t[1] - ry * t[0]);
-        } else {
-            acc_add(T[2], rx * t[1] - ry * t[0]);
+        double q0[U], q1[U], q2[U];
+        int tot[U];
+#pragma unroll
+        for (int u = 0; u < U; u++) {
+            q0[u] = a.q[nn[u]];
+            q1[u] = a.q[N + nn[u]];
+            q2[u] = D == 3 ? a.q[2 * N + nn[u]] : 0.0;
+            tot[u] = a.ctot[nn[u]];
+        }
+#pragma unroll
+        for (int u = 0; u < U; u++) {
+            if (cnt[u] == 0) continue;
+            const double sh = (double)cnt[u] / (double)tot[u];
+            const double t0 = sh * q0[u], t1 = sh * q1[u];
+            const double rx = rr[u][0], ry = rr[u][1];
+            acc_add(F[0], t0);
+            acc_add(F[1], t1);
+            if (D == 3) {
+                const double t2 = sh * q2[u];
+                const double rz = rr[u][2];
+                acc_add(F[2], t2);
+                acc_add(T[0], ry * t2 - rz * t1);
+                acc_add(T[1], rz * t0 - rx * t2);
+                acc_add(T[2], rx * t1 - ry * t0);
+            } else {
+                acc_add(T[2], rx * t1 - ry * t0);
+            }
         }
     }
 #pragma unroll
@@ -252,7 +291,25 @@ __global__ __launch_bounds__(256) void k_force(ForceArgs a) {
             acc_merge(T[d], o);
         }
     }
-    if (lane == 0) {
+    if (lane == 0)
+        for (int d = 0; d < 3; d++) {
+            part[wave][2 * d] = F[d].s;
+            part[wave][2 * d + 1] = F[d].c;
+            part[wave][6 + 2 * d] = T[d].s;
+            part[wave][6 + 2 * d + 1] = T[d].c;
+        }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < nw; w++)
+            for (int d = 0; d < 3; d++) {
+                Acc o;
+                o.s = part[w][2 * d];
+                o.c = part[w][2 * d + 1];
+                acc_merge(F[d], o);
+                o.s = part[w][6 + 2 * d];
+                o.c = part[w][6 + 2 * d + 1];
+                acc_merge(T[d], o);
+            }
         for (int d = 0; d < 3; d++) {
             double fv = -(F[d].s + F[d].c);
             double tv = -(T[d].s + T[d].c);
@@ -331,64 +388,75 @@ __device__ __forceinline__ bool pair_force(const CellArgs &a, int i, int j, doub
     return true;
 }
 
-// One thread per particle: collect touching neighbours from the 3^D cells,
-// sort them by id and add the pair forces in ascending id, then the walls.
-__global__ void k_dem(CellArgs a) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+// One wavefront per particle: each lane scans one neighbour cell, touching
+// neighbours are gathered in LDS, sorted by id, and the pair forces are added
+// in ascending id (then the walls) by the first lane.
+__global__ __launch_bounds__(256) void k_dem(CellArgs a) {
+    __shared__ int list[4][MAX_CONTACTS];
+    __shared__ int nlist[4];
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int i = blockIdx.x * 4 + wave;
     const int P = a.P.np;
-    if (i >= P) return;
     const int D = a.D;
-    const int c0 = cell_coord(a, 0, a.P.x[i]);
-    const int c1 = cell_coord(a, 1, a.P.x[P + i]);
-    const int c2 = D == 3 ? cell_coord(a, 2, a.P.x[2 * P + i]) : 0;
-    int ox[3], oy[3], oz[3];
-    const int nxc = axis_cells(c0, a.ncx, true, ox);
-    const int nyc = axis_cells(c1, a.ncy, !a.g.wall_y, oy);
-    int nzc = 1;
-    oz[0] = 0;
-    if (D == 3) nzc = axis_cells(c2, a.ncz, true, oz);
-    int list[MAX_CONTACTS];
-    int nl = 0;
-    for (int kz = 0; kz < nzc; kz++)
-        for (int ky = 0; ky < nyc; ky++)
-            for (int kx = 0; kx < nxc; kx++) {
-                const int c = ox[kx] + a.ncx * (oy[ky] + a.ncy * oz[kz]);
-                const int cnt = min(a.cell_count[c], CELL_CAP);
-                for (int s = 0; s < cnt; s++) {
-                    const int j = a.cell_ids[c * CELL_CAP + s];
-                    if (j == i) continue;
-                    if (!pair_force(a, i, j, nullptr)) continue;
-                    if (nl < MAX_CONTACTS) list[nl++] = j;
-                    else atomicOr(a.flags, FLAG_CONTACT_OVERFLOW);
-                }
+    if (lane == 0) nlist[wave] = 0;
+    __syncthreads();
+    if (i < P) {
+        const int c0 = cell_coord(a, 0, a.P.x[i]);
+        const int c1 = cell_coord(a, 1, a.P.x[P + i]);
+        const int c2 = D == 3 ? cell_coord(a, 2, a.P.x[2 * P + i]) : 0;
+        int ox[3], oy[3], oz[3];
+        const int nxc = axis_cells(c0, a.ncx, true, ox);
+        const int nyc = axis_cells(c1, a.ncy, !a.g.wall_y, oy);
+        int nzc = 1;
+        oz[0] = 0;
+        if (D == 3) nzc = axis_cells(c2, a.ncz, true, oz);
+        if (lane < nxc * nyc * nzc) {
+            const int kx = lane % nxc, ky = (lane / nxc) % nyc, kz = lane / (nxc * nyc);
+            const int c = ox[kx] + a.ncx * (oy[ky] + a.ncy * oz[kz]);
+            const int cnt = min(a.cell_count[c], CELL_CAP);
+            for (int s = 0; s < cnt; s++) {
+                const int j = a.cell_ids[c * CELL_CAP + s];
+                if (j == i) continue;
+                if (!pair_force(a, i, j, nullptr)) continue;
+                const int slot = atomicAdd(&nlist[wave], 1);
+                if (slot < MAX_CONTACTS) list[wave][slot] = j;
+                else atomicOr(a.flags, FLAG_CONTACT_OVERFLOW);
             }
-    for (int s = 1; s < nl; s++) {
-        const int v = list[s];
-        int t = s - 1;
-        while (t >= 0 && list[t] > v) {
-            list[t + 1] = list[t];
-            t--;
-        }
-        list[t + 1] = v;
-    }
-    double F[3] = {0.0, 0.0, 0.0};
-    for (int s = 0; s < nl; s++) pair_force(a, i, list[s], F);
-    if (a.g.wall_y) {
-        const double eta = a.ce * sqrt(a.P.m[i] * a.kn);
-        const double y = a.P.x[P + i];
-        const double vy = a.P.v[P + i];
-        const double dl = a.P.R[i] - (y + 0.5);
-        if (dl > 0.0) {
-            const double fmag = a.kn * dl - eta * vy;
-            F[1] = F[1] + fmag;
-        }
-        const double du = a.P.R[i] - ((a.g.Ly - 0.5) - y);
-        if (du > 0.0) {
-            const double fmag = a.kn * du - eta * (-vy);
-            F[1] = F[1] - fmag;
         }
     }
-    for (int d = 0; d < 3; d++) a.P.Fc[d * P + i] = F[d];
+    __syncthreads();
+    if (i < P && lane == 0) {
+        int *l = list[wave];
+        const int nl = min(nlist[wave], MAX_CONTACTS);
+        for (int s = 1; s < nl; s++) {
+            const int v = l[s];
+            int t = s - 1;
+            while (t >= 0 && l[t] > v) {
+                l[t + 1] = l[t];
+                t--;
+            }
+            l[t + 1] = v;
+        }
+        double F[3] = {0.0, 0.0, 0.0};
+        for (int s = 0; s < nl; s++) pair_force(a, i, l[s], F);
+        if (a.g.wall_y) {
+            const double eta = a.ce * sqrt(a.P.m[i] * a.kn);
+            const double y = a.P.x[P + i];
+            const double vy = a.P.v[P + i];
+            const double dl = a.P.R[i] - (y + 0.5);
+            if (dl > 0.0) {
+                const double fmag = a.kn * dl - eta * vy;
+                F[1] = F[1] + fmag;
+            }
+            const double du = a.P.R[i] - ((a.g.Ly - 0.5) - y);
+            if (du > 0.0) {
+                const double fmag = a.kn * du - eta * (-vy);
+                F[1] = F[1] - fmag;
+            }
+        }
+        for (int d = 0; d < 3; d++) a.P.Fc[d * P + i] = F[d];
+    }
 }
 
 __device__ __forceinline__ double wrap_pos(double x, double L) {
@@ -436,20 +504,50 @@ hipError_t launch_foot_bbox(const FootArgs &a, int D, hipStream_t s) {
 
 hipError_t launch_foot_clear(const FootArgs &a, hipStream_t s) {
     if (a.P.np == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_foot_clear, dim3((unsigned)a.P.np), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(k_foot_clear, dim3((unsigned)a.P.np), dim3(a.g.nz == 1 ? 128 : 256), 0, s, a);
+    return hipGetLastError();
+}
+
+template <int D>
+static hipError_t paint_s(const FootArgs &a, hipStream_t s, int block) {
+    const dim3 g((unsigned)a.P.np), b((unsigned)block);
+    switch (a.S) {
+        case 1: hipLaunchKernelGGL((k_foot_paint<D, 1>), g, b, 0, s, a); break;
+        case 2: hipLaunchKernelGGL((k_foot_paint<D, 2>), g, b, 0, s, a); break;
+        case 3: hipLaunchKernelGGL((k_foot_paint<D, 3>), g, b, 0, s, a); break;
+        case 4: hipLaunchKernelGGL((k_foot_paint<D, 4>), g, b, 0, s, a); break;
+        case 5: hipLaunchKernelGGL((k_foot_paint<D, 5>), g, b, 0, s, a); break;
+        case 6: hipLaunchKernelGGL((k_foot_paint<D, 6>), g, b, 0, s, a); break;
+        case 7: hipLaunchKernelGGL((k_foot_paint<D, 7>), g, b, 0, s, a); break;
+        default: hipLaunchKernelGGL((k_foot_paint<D, 8>), g, b, 0, s, a); break;
+    }
     return hipGetLastError();
 }
 
 hipError_t launch_foot_paint(const FootArgs &a, int D, hipStream_t s) {
     if (a.P.np == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_foot_paint, dim3((unsigned)a.P.np), dim3(256), 0, s, a, D);
+    return D == 2 ? paint_s<2>(a, s, 128) : paint_s<3>(a, s, 256);
+}
+
+template <int D>
+static hipError_t force_s(const ForceArgs &a, hipStream_t s, int block) {
+    const dim3 g((unsigned)a.P.np), b((unsigned)block);
+    switch (a.S) {
+        case 1: hipLaunchKernelGGL((k_force<D, 1>), g, b, 0, s, a); break;
+        case 2: hipLaunchKernelGGL((k_force<D, 2>), g, b, 0, s, a); break;
+        case 3: hipLaunchKernelGGL((k_force<D, 3>), g, b, 0, s, a); break;
+        case 4: hipLaunchKernelGGL((k_force<D, 4>), g, b, 0, s, a); break;
+        case 5: hipLaunchKernelGGL((k_force<D, 5>), g, b, 0, s, a); break;
+        case 6: hipLaunchKernelGGL((k_force<D, 6>), g, b, 0, s, a); break;
+        case 7: hipLaunchKernelGGL((k_force<D, 7>), g, b, 0, s, a); break;
+        default: hipLaunchKernelGGL((k_force<D, 8>), g, b, 0, s, a); break;
+    }
     return hipGetLastError();
 }
 
 hipError_t launch_force(const ForceArgs &a, hipStream_t s) {
     if (a.P.np == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_force, dim3(blocks_for(a.P.np, 4)), dim3(256), 0, s, a);
-    return hipGetLastError();
+    return a.D == 2 ? force_s<2>(a, s, 64) : force_s<3>(a, s, 256);
 }
 
 hipError_t launch_cells(const CellArgs &a, hipStream_t s) {
@@ -462,7 +560,7 @@ hipError_t launch_cells(const CellArgs &a, hipStream_t s) {
 
 hipError_t launch_dem(const CellArgs &a, hipStream_t s) {
     if (a.P.np == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_dem, dim3(blocks_for(a.P.np, 128)), dim3(128), 0, s, a);
+    hipLaunchKernelGGL(k_dem, dim3(blocks_for(a.P.np, 4)), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 

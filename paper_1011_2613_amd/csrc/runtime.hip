@@ -34,7 +34,7 @@ struct Layout {
     int64_t N;
     int P;
     int64_t cell_budget;
-    size_t off_fA, off_fB, off_nown, off_slots, off_q, off_beta, off_arel;
+    size_t off_fA, off_fB, off_nown, off_slots, off_q, off_ctot, off_beta, off_arel;
     size_t off_x, off_v, off_w, off_R, off_m, off_I, off_fixed, off_Fh, off_Th, off_Fc, off_bb;
     size_t off_cc, off_cid, off_flags, total;
 };
@@ -75,6 +75,7 @@ Layout make_layout(const lbm_config *c) {
     L.off_nown = take(((size_t)L.N + 3) / 4 * 4);
     L.off_slots = take((size_t)MAX_OWNERS * L.N * 4);
     L.off_q = take((size_t)L.D * L.N * 8);
+    L.off_ctot = take((size_t)L.N * 4);
     L.off_beta = take((size_t)(L.Smax + 1) * 8);
     L.off_arel = take((size_t)(L.Smax + 1) * 8);
     const size_t P = (size_t)L.P;
@@ -205,6 +206,7 @@ LBArgs lb_args(lbm_ctx *c, int from) {
     a.beta_tab = wsp<double>(c, c->L.off_beta);
     a.arel_tab = wsp<double>(c, c->L.off_arel);
     a.q = wsp<double>(c, c->L.off_q);
+    a.ctot = wsp<int>(c, c->L.off_ctot);
     a.px = wsp<double>(c, c->L.off_x);
     a.pv = wsp<double>(c, c->L.off_v);
     a.pw = wsp<double>(c, c->L.off_w);
@@ -259,8 +261,7 @@ hipError_t enqueue_step(lbm_ctx *c, int from, hipStream_t s) {
         ForceArgs fo;
         fo.P = particles(c);
         fo.g = c->g;
-        fo.nown = wsp<uint8_t>(c, c->L.off_nown);
-        fo.slots = wsp<uint32_t>(c, c->L.off_slots);
+        fo.ctot = wsp<int>(c, c->L.off_ctot);
         fo.q = wsp<double>(c, c->L.off_q);
         fo.S = c->cfg.eps_samples;
         fo.D = c->L.D;

@@ -10,9 +10,12 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
 def declared():
-    hdr = open(os.path.join(ROOT, "include", "lbimb.h")).read()
-    hdr = re.sub(r"/\*.*?\*/", "", hdr, flags=re.S)
-    return sorted(set(re.findall(r"\b(lbm_[a-z_]+)\s*\(", hdr)))
+    names = set()
+    for h in ("lbimb.h", "mlp_closure.h"):
+        hdr = open(os.path.join(ROOT, "include", h)).read()
+        hdr = re.sub(r"/\*.*?\*/", "", hdr, flags=re.S)
+        names |= set(re.findall(r"\b((?:lbm|mlp)_[a-z_]+)\s*\(", hdr))
+    return sorted(names)
 
 
 def test_header_declares_the_boundary_calls():
