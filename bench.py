@@ -82,6 +82,54 @@ def run_variant(binding, inputs, w, parts, storage, steps, warmup):
     }
 
 
+def ensemble_bench(binding, nbox=128, steps=100):
+    """Batched drag ensemble: boxes as in the drag-data workload (edges 32-96,
+    1-64 spheres of radius 4-8), autotuned tile shape and launch mode, FP32
+    shifted storage; lattice updates per second over all boxes."""
+    import torch
+    from paper_1011_2613_amd import ensemble as E
+    boxes = E.sample_boxes(nbox, 4)
+    b = binding.Batch(boxes, samples=4)
+    tune = b.autotune(steps=5)
+    b.run(10, tune["mode"])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b.run(steps, tune["mode"])
+    t1 = time.perf_counter()
+    nodes = sum(x["edge"] ** 3 for x in boxes)
+    mlups = nodes * steps / (t1 - t0) / 1e6
+    gbs = mlups * 1e6 * 152 / 1e9
+    b.close()
+    torch.cuda.empty_cache()
+    return {"value": round(mlups, 1), "unit": "MLUPS", "boxes": nbox, "nodes": nodes,
+            "spheres": int(sum(len(x["pos"]) for x in boxes)), "steps": steps,
+            "mode": "persistent" if tune["mode"] == 1 else "per-step", "tile_rows": tune["rows"],
+            "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": round(gbs / HBM_PEAK_GBS, 4)}}
+
+
+def closure_bench(binding, rows=1 << 20, reps=10):
+    """MLP drag closure inference (bfloat16 MFMA, binary32 accumulate)."""
+    import torch
+    from paper_1011_2613_amd import inputs
+    m = binding.Mlp(max_batch=64)
+    m.set_params(binding.mlp_pack(inputs.mlp_initial_params(3)))
+    X = torch.randn(rows, 40, device="cuda:0")
+    m.forward(X)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        m.forward(X)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / reps
+    flops = 2.0 * (40 * 128 + 128 * 128 * 2 + 128) * rows
+    tf = flops / dt / 1e12
+    m.close()
+    return {"value": round(rows / dt / 1e6, 2), "unit": "M rows/s", "rows": rows,
+            "roofline": {"bound": "mfma", "achieved": round(tf, 2), "peak": 2500.0, "unit": "TFLOP/s",
+                         "frac": round(tf / 2500.0, 4)}}
+
+
 def cpu_baseline(w, parts):
     """The FP64 CPU oracle, single thread, one full step of the same workload."""
     from oracle import oracle as O
@@ -127,6 +175,8 @@ def main():
     ap.add_argument("--workload", default="C3")
     ap.add_argument("--variants", default="fp64,fp32s,fp16s")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the batched-ensemble and closure measurements")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 2 GiB device copy (counter calibration)")
     args = ap.parse_args()
@@ -178,6 +228,11 @@ def main():
                      for v, r in res.items() if v != "fp64"},
         "device": torch.cuda.get_device_name(0),
     }
+    if not args.no_extras:
+        out["ensemble"] = ensemble_bench(binding)
+        print("# ensemble: %s" % out["ensemble"], file=sys.stderr, flush=True)
+        out["closure"] = closure_bench(binding)
+        print("# closure: %s" % out["closure"], file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, parts)
     print(json.dumps(out), flush=True)

@@ -40,7 +40,7 @@ enum {
     LBM_E_INVALID = -1,          /* bad argument or configuration */
     LBM_E_NOMEM = -2,            /* workspace too small */
     LBM_E_HIP = -3,              /* a HIP runtime call failed */
-    LBM_E_NONFINITE = -4,        /* a non-finite value was found in the state */
+    LBM_E_NONFINITE = -4,        /* a non-finite value in the state, or a particle centre outside the box */
     LBM_E_SLOT_OVERFLOW = -5,    /* more than LBM_MAX_OWNERS particles cover one node */
     LBM_E_STATE = -6,            /* call out of order (e.g. step before particles) */
     LBM_E_IO = -7,               /* save/load file error */
@@ -78,6 +78,8 @@ typedef struct lbm_config {
     double kn;              /* DEM normal stiffness (Eq. 4) */
     double restitution;     /* DEM restitution coefficient e, 0 < e <= 1 (Eq. 5) */
     int max_particles;      /* capacity reserved in the workspace */
+    double max_radius;      /* largest particle radius the workspace is sized for
+                               (<= 0 selects 8 lattice units) */
 } lbm_config;
 
 typedef struct lbm_ctx lbm_ctx;
@@ -100,7 +102,7 @@ void lbm_destroy(lbm_ctx *ctx);
  * reported).  Mass is rho_s pi R^2 (disc of unit depth) or rho_s 4/3 pi R^3,
  * moment of inertia m R^2 / 2 or 2 m R^2 / 5.  `fixed` may be NULL.  Host
  * pointers only for this call (ptr_kind must be LBM_HOST).  Errors:
- * LBM_E_INVALID (n > max_particles, radius <= 0, a particle wider than the
+ * LBM_E_INVALID (n > max_particles, radius <= 0 or > max_radius, a particle wider than the
  * periodic box, a centre outside the box, two particles overlapping by more
  * than half the smaller radius). */
 int lbm_set_particles(lbm_ctx *ctx, int64_t n, const double *pos, const double *vel,
@@ -164,6 +166,71 @@ int lbm_get_timing(lbm_ctx *ctx, double *ms, int64_t *launches);
  * mismatching file gives LBM_E_INVALID. */
 int lbm_save(lbm_ctx *ctx, const char *path);
 int lbm_load(lbm_ctx *ctx, const char *path);
+
+/* ------------------------------------------------ batched drag ensemble
+ * Many small fully periodic cubic D3Q19 boxes, each with fixed equal spheres
+ * and its own tau and fluid body force, advanced together in shifted FP32
+ * storage (drag-data generation).  The per-node arithmetic is that of
+ * lbm_step with LBM_FP32_SHIFTED and particles at rest, so a box gives the
+ * same bits in a batch as alone.  Sphere footprints are computed once at
+ * creation (sub-cell sampling with eps_samples per axis). */
+typedef struct lbm_box {
+    int edge;                /* box edge L (L x L x L nodes), 2R + 2 <= L */
+    double tau;              /* > 1/2 */
+    double fluid_force[3];   /* body force per unit mass on the fluid */
+    int nspheres;            /* >= 0 */
+    const double *pos;       /* [nspheres][3], centres in [0, L) */
+    double radius;           /* sphere radius R */
+    double init_velocity[3]; /* uniform fluid velocity of the initial state,
+                                f = f^eq(1, init_velocity); |u| <= 0.2 */
+} lbm_box;
+
+typedef struct lbm_batch lbm_batch;
+
+enum { LBM_BATCH_PER_STEP = 0, LBM_BATCH_PERSISTENT = 1 };
+
+int lbm_batch_workspace_bytes(const lbm_box *boxes, int nbox, int eps_samples, size_t *bytes);
+
+/* Copies the box descriptions (sphere positions included), computes the
+ * footprints and sets every box to its initial state (uniform density 1 and
+ * velocity init_velocity, rest when zero).  Errors: LBM_E_INVALID, LBM_E_NOMEM,
+ * LBM_E_HIP, LBM_E_SLOT_OVERFLOW (a node covered by more than 4 spheres). */
+int lbm_batch_create(const lbm_box *boxes, int nbox, int eps_samples, void *workspace,
+                     size_t ws_bytes, void *hip_stream, lbm_batch **out);
+void lbm_batch_destroy(lbm_batch *b);
+
+/* Tile shape: lattice rows (of L nodes) per workgroup for the boxes of the
+ * given edge; rows must divide L*L. */
+int lbm_batch_set_tile_rows(lbm_batch *b, int edge, int rows);
+
+/* Advances every active box by nsteps, either with one launch per step
+ * (LBM_BATCH_PER_STEP) or with one persistent launch (LBM_BATCH_PERSISTENT).
+ * Synchronises and checks the error flags.  Errors: LBM_E_HIP, LBM_E_STATE
+ * (a persistent wait hit its bound). */
+int lbm_batch_run(lbm_batch *b, int64_t nsteps, int mode);
+
+/* Boxes with active[b] == 0 are no longer advanced (retired). */
+int lbm_batch_set_active(lbm_batch *b, const uint8_t *active);
+
+/* Hydrodynamic force and torque on every sphere from the last step, spheres
+ * numbered box by box in input order, [total][3] binary64 (Eq. 3). */
+int lbm_batch_forces(lbm_batch *b, double *F, double *T, int ptr_kind);
+
+/* Superficial mean fluid velocity (1/N) sum_n sum_i f_i c_i of every box,
+ * [nbox][3] binary64. */
+int lbm_batch_mean_velocity(lbm_batch *b, double *U, int ptr_kind);
+
+/* Pre-collision populations f_i = w_i + g_i of one box, [19][L^3] binary64. */
+int lbm_batch_get_distributions(lbm_batch *b, int box, double *f, int ptr_kind);
+
+/* Times every tile shape (rows 1, 2, 4, 8, 16) for each edge present and
+ * both run modes over `steps` steps, keeps the fastest, and returns the boxes
+ * to rest at time 0.  rows_out[k] and ms_out[k] (may be NULL) receive, for the
+ * k-th distinct edge in ascending order, the chosen rows and the step time. */
+int lbm_batch_autotune(lbm_batch *b, int steps, int *edges_out, int *rows_out, int *mode_out,
+                       double *ms_per_step_out);
+
+int64_t lbm_batch_time(const lbm_batch *b);
 
 const char *lbm_error_string(int code);
 const char *lbm_last_error(const lbm_ctx *ctx);

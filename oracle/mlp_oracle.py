@@ -39,18 +39,9 @@ def dsilu(z):
 
 
 def init_params(seed):
-    """Kaiming-uniform weights (bound sqrt(6/fan_in)) and zero biases, from a
-    SplitMix64 stream so the GPU side draws the same numbers from its input."""
+    """Seeded initial weights, drawn by the shared input generator."""
     from paper_1011_2613_amd import inputs as I
-    params = []
-    pos = 0
-    for fin, fout in zip(SIZES[:-1], SIZES[1:]):
-        bound = np.sqrt(6.0 / fin)
-        u = I.uniform(seed, pos, fin * fout)
-        pos += fin * fout
-        W = ((u * 2.0 - 1.0) * bound).reshape(fout, fin).astype(np.float32).astype(np.float64)
-        params.append([W, np.zeros(fout)])
-    return params
+    return I.mlp_initial_params(seed, SIZES)
 
 
 def _q(x, on):

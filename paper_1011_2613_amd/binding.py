@@ -30,7 +30,7 @@ class lbm_config(C.Structure):
                 ("nz", C.c_int), ("wall_y", C.c_int), ("tau", C.c_double),
                 ("fluid_force", C.c_double * 3), ("particle_accel", C.c_double * 3),
                 ("eps_samples", C.c_int), ("kn", C.c_double), ("restitution", C.c_double),
-                ("max_particles", C.c_int)]
+                ("max_particles", C.c_int), ("max_radius", C.c_double)]
 
 
 class LbmError(RuntimeError):
@@ -46,7 +46,10 @@ _SYMBOLS = ("lbm_workspace_bytes", "lbm_create", "lbm_destroy", "lbm_set_particl
             "lbm_time", "lbm_particle_count", "lbm_set_timing", "lbm_get_timing", "lbm_save", "lbm_load",
             "lbm_error_string", "lbm_last_error",
             "mlp_workspace_bytes", "mlp_create", "mlp_destroy", "mlp_set_params", "mlp_get_params",
-            "mlp_forward", "mlp_gradients", "mlp_train_step")
+            "mlp_forward", "mlp_gradients", "mlp_train_step",
+            "lbm_batch_workspace_bytes", "lbm_batch_create", "lbm_batch_destroy", "lbm_batch_set_tile_rows",
+            "lbm_batch_run", "lbm_batch_set_active", "lbm_batch_forces", "lbm_batch_mean_velocity",
+            "lbm_batch_get_distributions", "lbm_batch_autotune", "lbm_batch_time")
 
 
 def load():
@@ -89,8 +92,8 @@ def load():
     L.lbm_last_error.argtypes = [vp]
     L.lbm_last_error.restype = C.c_char_p
     for name in _SYMBOLS:
-        if name.startswith("lbm_") and name not in ("lbm_destroy", "lbm_time", "lbm_particle_count",
-                                                    "lbm_error_string", "lbm_last_error"):
+        if name.startswith("lbm_") and not name.startswith("lbm_batch_") and name not in (
+                "lbm_destroy", "lbm_time", "lbm_particle_count", "lbm_error_string", "lbm_last_error"):
             getattr(L, name).restype = C.c_int
     _lib = L
     return L
@@ -121,7 +124,7 @@ class Simulation:
 
     def __init__(self, dim, shape, tau, storage="fp64", wall_y=False, fluid_force=(0, 0, 0),
                  particle_accel=(0, 0, 0), samples=4, kn=0.0, restitution=0.9,
-                 max_particles=1, device="cuda:0"):
+                 max_particles=1, max_radius=0.0, device="cuda:0"):
         import torch
         self._torch = torch
         L = load()
@@ -146,6 +149,7 @@ class Simulation:
         cfg.kn = float(kn)
         cfg.restitution = float(restitution)
         cfg.max_particles = int(max_particles)
+        cfg.max_radius = float(max_radius)
         self.cfg = cfg
         nbytes = C.c_size_t(0)
         self._check(L.lbm_workspace_bytes(C.byref(cfg), C.byref(nbytes)))
@@ -409,3 +413,142 @@ def mlp_unpack(p):
 
 def mlp_pack(params):
     return np.concatenate([np.concatenate([np.asarray(W).ravel(), np.asarray(b).ravel()]) for W, b in params])
+
+
+# ------------------------------------------------------ batched ensemble
+class lbm_box(C.Structure):
+    _fields_ = [("edge", C.c_int), ("tau", C.c_double), ("fluid_force", C.c_double * 3),
+                ("nspheres", C.c_int), ("pos", C.POINTER(C.c_double)), ("radius", C.c_double),
+                ("init_velocity", C.c_double * 3)]
+
+
+LBM_BATCH_PER_STEP, LBM_BATCH_PERSISTENT = 0, 1
+
+
+def _load_batch(L):
+    if getattr(L, "_batch_ready", False):
+        return L
+    vp, i64 = C.c_void_p, C.c_int64
+    bp = C.POINTER(lbm_box)
+    L.lbm_batch_workspace_bytes.argtypes = [bp, C.c_int, C.c_int, C.POINTER(C.c_size_t)]
+    L.lbm_batch_create.argtypes = [bp, C.c_int, C.c_int, vp, C.c_size_t, vp, C.POINTER(vp)]
+    L.lbm_batch_destroy.argtypes = [vp]
+    L.lbm_batch_destroy.restype = None
+    L.lbm_batch_set_tile_rows.argtypes = [vp, C.c_int, C.c_int]
+    L.lbm_batch_run.argtypes = [vp, i64, C.c_int]
+    L.lbm_batch_set_active.argtypes = [vp, vp]
+    L.lbm_batch_forces.argtypes = [vp, vp, vp, C.c_int]
+    L.lbm_batch_mean_velocity.argtypes = [vp, vp, C.c_int]
+    L.lbm_batch_get_distributions.argtypes = [vp, C.c_int, vp, C.c_int]
+    L.lbm_batch_autotune.argtypes = [vp, C.c_int, vp, vp, vp, vp]
+    L.lbm_batch_time.argtypes = [vp]
+    L.lbm_batch_time.restype = i64
+    for n in ("lbm_batch_workspace_bytes", "lbm_batch_create", "lbm_batch_set_tile_rows", "lbm_batch_run",
+              "lbm_batch_set_active", "lbm_batch_forces", "lbm_batch_mean_velocity",
+              "lbm_batch_get_distributions", "lbm_batch_autotune"):
+        getattr(L, n).restype = C.c_int
+    L._batch_ready = True
+    return L
+
+
+class Batch:
+    """Batched ensemble of periodic D3Q19 boxes with fixed spheres (shifted
+    FP32).  boxes: list of dicts with keys edge, tau, fluid_force (3),
+    pos ([n, 3] array), radius and optionally init_velocity (3)."""
+
+    def __init__(self, boxes, samples=4, device="cuda:0"):
+        import torch
+        self._torch = torch
+        L = _load_batch(load())
+        self.nbox = len(boxes)
+        self._pos = []
+        arr = (lbm_box * self.nbox)()
+        self.edges = []
+        self.counts = []
+        for b, d in enumerate(boxes):
+            pos = np.ascontiguousarray(np.asarray(d.get("pos", np.zeros((0, 3))), dtype=np.float64).reshape(-1, 3))
+            self._pos.append(pos)
+            arr[b].edge = int(d["edge"])
+            arr[b].tau = float(d["tau"])
+            ff = list(d.get("fluid_force", (0, 0, 0))) + [0.0] * 3
+            for a in range(3):
+                arr[b].fluid_force[a] = float(ff[a])
+            arr[b].nspheres = pos.shape[0]
+            arr[b].pos = pos.ctypes.data_as(C.POINTER(C.c_double)) if pos.shape[0] else None
+            arr[b].radius = float(d.get("radius", 1.0))
+            u0 = list(d.get("init_velocity", (0, 0, 0))) + [0.0] * 3
+            for a in range(3):
+                arr[b].init_velocity[a] = float(u0[a])
+            self.edges.append(int(d["edge"]))
+            self.counts.append(pos.shape[0])
+        self._arr = arr
+        self.nsph = int(sum(self.counts))
+        nbytes = C.c_size_t(0)
+        rc = L.lbm_batch_workspace_bytes(arr, self.nbox, int(samples), C.byref(nbytes))
+        if rc:
+            raise LbmError(rc, "lbm_batch_workspace_bytes")
+        self.device = torch.device(device)
+        self.workspace = torch.empty(int(nbytes.value) + 256, dtype=torch.uint8, device=self.device)
+        aligned = (self.workspace.data_ptr() + 255) // 256 * 256
+        self.stream = torch.cuda.Stream(device=self.device)
+        h = C.c_void_p()
+        rc = L.lbm_batch_create(arr, self.nbox, int(samples), C.c_void_p(aligned), nbytes,
+                                C.c_void_p(self.stream.cuda_stream), C.byref(h))
+        if rc:
+            raise LbmError(rc, "lbm_batch_create")
+        self._ctx = h
+
+    def close(self):
+        if getattr(self, "_ctx", None):
+            load().lbm_batch_destroy(self._ctx)
+            self._ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _chk(self, rc, what):
+        if rc:
+            raise LbmError(rc, what)
+
+    @property
+    def t(self):
+        return int(load().lbm_batch_time(self._ctx))
+
+    def set_tile_rows(self, edge, rows):
+        self._chk(load().lbm_batch_set_tile_rows(self._ctx, int(edge), int(rows)), "set_tile_rows")
+
+    def run(self, nsteps, mode=LBM_BATCH_PER_STEP):
+        self._chk(load().lbm_batch_run(self._ctx, int(nsteps), int(mode)), "lbm_batch_run")
+
+    def set_active(self, active):
+        a = np.ascontiguousarray(np.asarray(active, dtype=np.uint8).reshape(self.nbox))
+        self._chk(load().lbm_batch_set_active(self._ctx, _ptr(a)), "set_active")
+
+    def forces(self):
+        n = max(self.nsph, 1)
+        F = np.zeros((n, 3)); T = np.zeros((n, 3))
+        self._chk(load().lbm_batch_forces(self._ctx, _ptr(F), _ptr(T), LBM_HOST), "forces")
+        return F[: self.nsph], T[: self.nsph]
+
+    def mean_velocity(self):
+        U = np.zeros((self.nbox, 3))
+        self._chk(load().lbm_batch_mean_velocity(self._ctx, _ptr(U), LBM_HOST), "mean_velocity")
+        return U
+
+    def get_f(self, box):
+        L = self.edges[box]
+        f = np.empty((19, L, L, L))
+        self._chk(load().lbm_batch_get_distributions(self._ctx, int(box), _ptr(f), LBM_HOST), "get_f")
+        return f
+
+    def autotune(self, steps=20):
+        ne = len(set(self.edges))
+        edges = np.zeros(ne, dtype=np.int32); rows = np.zeros(ne, dtype=np.int32)
+        mode = np.zeros(1, dtype=np.int32); ms = np.zeros(1)
+        self._chk(load().lbm_batch_autotune(self._ctx, int(steps), _ptr(edges), _ptr(rows), _ptr(mode), _ptr(ms)),
+                  "autotune")
+        return {"rows": {int(e): int(r) for e, r in zip(edges, rows)}, "mode": int(mode[0]),
+                "ms_per_step": float(ms[0])}

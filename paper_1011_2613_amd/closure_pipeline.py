@@ -1,0 +1,139 @@
+"""Learned drag closure, end to end: drag ensembles of batched LB-IMB boxes
+with fixed spheres, training of the BF16-MFMA closure on their per-particle
+drag, and evaluation on held-out boxes against the resolved drag, with the
+resolved drag as fallback outside the training envelope.
+
+    python -m paper_1011_2613_amd.closure_pipeline --ensembles 4 --boxes 512 \
+        --heldout 64 --out closure.json
+
+Training ensembles use box seeds 1000 + e (e = 0 .. ensembles-1), the
+held-out boxes seed 9000, so no held-out box is seen in training.  Every
+lattice step, force sum and network evaluation runs in the HIP library.
+"""
+import argparse
+import json
+import math
+import time
+
+import numpy as np
+
+from . import binding
+from . import ensemble as E
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def run_ensemble(boxes, samples=4, max_steps=20000, check_every=500, tol=1e-5, tune_steps=10, tune_cache=None,
+                 log=say):
+    """Runs one batch of boxes to steady drag.  Returns the dataset of its
+    steady boxes and the run's statistics."""
+    import torch
+    t0 = time.perf_counter()
+    b = binding.Batch(boxes, samples=samples)
+    tune = E.autotune_cached(b, tune_cache, steps=tune_steps)
+    nodes = np.array([bx["edge"] ** 3 for bx in boxes], dtype=np.float64)
+    log("  tile rows %s, mode %s (%s), %.1f M nodes"
+        % (tune["rows"], "persistent" if tune["mode"] else "per-step",
+           "cached" if tune["cached"] else "%.3f ms/step" % tune["ms_per_step"], nodes.sum() / 1e6))
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    steady, stop = E.run_to_steady(b, boxes, check_every=check_every, max_steps=max_steps, tol=tol,
+                                   mode=tune["mode"], log=log)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    U = b.mean_velocity()
+    X, y, box_of = E.drag_dataset(boxes, b, steady, U)
+    updates = float((nodes * stop).sum())
+    stats = {"boxes": len(boxes), "steady_boxes": int(steady.sum()), "samples": int(len(y)),
+             "node_updates": updates, "run_s": t2 - t1, "setup_s": t1 - t0,
+             "mlups": updates / (t2 - t1) / 1e6, "mean_stop_step": float(np.mean(stop)),
+             "tile_rows": tune["rows"], "mode": tune["mode"]}
+    del b
+    return X, y, box_of, stats
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--ensembles", type=int, default=2)
+    ap.add_argument("--boxes", type=int, default=512)
+    ap.add_argument("--heldout", type=int, default=64)
+    ap.add_argument("--max-steps", type=int, default=20000)
+    ap.add_argument("--check-every", type=int, default=500)
+    ap.add_argument("--tol", type=float, default=1e-5)
+    ap.add_argument("--epochs", type=int, default=300)
+    ap.add_argument("--batch", type=int, default=4096)
+    ap.add_argument("--lr", type=float, default=1e-3)
+    ap.add_argument("--infer-rows", type=int, default=1 << 20)
+    ap.add_argument("--out", default=None)
+    ap.add_argument("--tune-cache", default=None, help="JSON file of tuned tile shapes (read and written)")
+    args = ap.parse_args(argv)
+    import torch
+    if not torch.cuda.is_available():
+        raise SystemExit("closure pipeline: no GPU visible")
+
+    Xs, ys, ens_stats = [], [], []
+    for e in range(args.ensembles):
+        boxes = E.sample_boxes(args.boxes, 1000 + e)
+        say("ensemble %d: %d boxes" % (e, len(boxes)))
+        X, y, _, st = run_ensemble(boxes, max_steps=args.max_steps, check_every=args.check_every, tol=args.tol,
+                                   tune_cache=args.tune_cache)
+        say("  steady %d/%d boxes, %d samples, %.1f s, %.0f MLUPS"
+            % (st["steady_boxes"], st["boxes"], st["samples"], st["run_s"], st["mlups"]))
+        Xs.append(X)
+        ys.append(y)
+        ens_stats.append(st)
+    Xtr, ytr = np.concatenate(Xs), np.concatenate(ys)
+
+    test_boxes = E.sample_boxes(args.heldout, 9000)
+    say("held-out: %d boxes" % len(test_boxes))
+    Xte, yte, _, test_stats = run_ensemble(test_boxes, max_steps=args.max_steps, check_every=args.check_every,
+                                           tol=args.tol, tune_cache=args.tune_cache)
+    say("  steady %d/%d boxes, %d samples" % (test_stats["steady_boxes"], test_stats["boxes"], test_stats["samples"]))
+
+    ok = np.isfinite(ytr) & (ytr > 0)
+    Xtr, ytr = Xtr[ok], ytr[ok]
+    t0 = time.perf_counter()
+    mlp, norm, losses = E.train_closure(Xtr, ytr, epochs=args.epochs, batch=args.batch, lr=args.lr, log=say)
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t0
+    steps_per_epoch = max(1, math.ceil(len(ytr) / args.batch))
+
+    res = E.evaluate(mlp, norm, Xte, yte)
+    res_train = E.evaluate(mlp, norm, Xtr[: min(len(ytr), 20000)], ytr[: min(len(ytr), 20000)])
+
+    # inference throughput on rows drawn from the training distribution,
+    # inputs already on the device
+    rows = np.asarray(E.I.uniform(77, 0, args.infer_rows) * len(Xtr), dtype=np.int64)
+    Xi = torch.as_tensor(norm(Xtr[rows]).astype(np.float32), device="cuda:0")
+    mlp.forward(Xi[:4096])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    mlp.forward(Xi)
+    torch.cuda.synchronize()
+    infer_s = time.perf_counter() - t0
+
+    resolved_s = sum(s["run_s"] for s in ens_stats)
+    resolved_n = sum(s["samples"] for s in ens_stats)
+    out = {
+        "train_samples": int(len(ytr)), "heldout_samples": int(len(yte)),
+        "ensembles": ens_stats, "heldout_run": test_stats,
+        "heldout": res, "train_subset": res_train,
+        "loss_first": losses[0], "loss_last": losses[-1],
+        "train_s": train_s, "train_samples_per_s": len(ytr) * args.epochs / train_s,
+        "train_steps": args.epochs * steps_per_epoch,
+        "inference_rows": int(args.infer_rows), "inference_s": infer_s,
+        "inference_rows_per_s": args.infer_rows / infer_s,
+        "resolved_s_per_drag_value": resolved_s / max(resolved_n, 1),
+        "closure_s_per_drag_value": infer_s / args.infer_rows,
+    }
+    say(json.dumps({k: v for k, v in out.items() if k not in ("ensembles",)}, indent=1))
+    if args.out:
+        with open(args.out, "w") as f:
+            json.dump(out, f, indent=1)
+    return out
+
+
+if __name__ == "__main__":
+    main()

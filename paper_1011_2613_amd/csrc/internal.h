@@ -39,6 +39,7 @@ enum : uint32_t {
     FLAG_CELL_OVERFLOW = 2u,
     FLAG_CONTACT_OVERFLOW = 4u,
     FLAG_NONFINITE = 8u,
+    FLAG_BATCH_TIMEOUT = 16u,
 };
 
 constexpr int MAX_OWNERS = 4;
@@ -52,7 +53,10 @@ struct Particles {
     double *R, *m, *I;     // radius, mass, moment of inertia
     uint8_t *fixed;
     double *Fh, *Th, *Fc;  // hydrodynamic force/torque, contact force
-    int *bb;               // [3][P] lower corner of the painted bounding box
+    int *bb;               // [6][P] painted bounding box, lower and upper corner
+    uint32_t *list;        // [P][list_cap] covered nodes: count | kx << 10 | ky << 17 | kz << 24
+    int *list_len;         // [P]
+    int list_cap;
     int np;
 };
 
@@ -100,7 +104,6 @@ struct ForceArgs {
     Geom g;
     const int *ctot;
     const double *q;
-    int S;
     int D;
 };
 
@@ -116,6 +119,51 @@ struct CellArgs {
     double ap[3];
 };
 
+// One periodic cubic box of the batched ensemble (fixed spheres).
+struct BatchBox {
+    int L;                 // edge
+    int rows;              // lattice rows per tile (tile shape)
+    int ntiles;            // L*L / rows
+    int tile0;             // first global tile index of the box
+    int64_t off;           // element offset of the box's populations in A / B
+    int64_t noff;          // node offset of the box in per-node arrays
+    int table;             // offset of the box's beta / (1-beta)/tau tables
+    int active;            // 0: retired (skipped)
+    float arel0f;          // 1 / tau
+    float cgf[19];         // c_i . g_fluid
+    float g0[19];          // initial shifted populations f^eq_i(1, u0) - w_i
+};
+
+struct BatchArgs {
+    float *A, *B;              // population pool, shifted storage
+    const BatchBox *boxes;
+    const int *tile_box;       // [ntiles] box of each global tile
+    const uint16_t *cnt;       // [total_nodes] static total sample count
+    const float *beta, *arel;  // per-box tables
+    float *q;                  // [3][total_nodes]
+    int64_t total_nodes;
+    int nbox, ntiles, Smax;
+    int *queue;                // persistent work counter
+    int *done;                 // [nbox] tiles finished (persistent mode)
+    uint32_t *flags;
+    // spheres
+    int nsph;
+    const int *sph_box;
+    const double *sph_x;       // [nsph][3] position in its box
+    const int *list_start;     // [nsph + 1]
+    const uint32_t *list;      // node | count << 20
+    double *F, *T;             // [nsph][3]
+};
+
+// launchers (batch.hip)
+hipError_t launch_batch_step(const BatchArgs &a, int parity, hipStream_t s);
+hipError_t launch_batch_persistent(const BatchArgs &a, int nsteps, int parity0, int grid, hipStream_t s);
+hipError_t launch_batch_force(const BatchArgs &a, hipStream_t s);
+hipError_t launch_batch_mean(const BatchArgs &a, int parity, double *U, hipStream_t s);
+hipError_t launch_batch_get_f(const BatchArgs &a, int b, int L, int parity, double *f, hipStream_t s);
+hipError_t launch_batch_init(const BatchArgs &a, int nbox, int maxL, hipStream_t s);
+int batch_persistent_grid();
+
 // launchers (lb_kernels.hip)
 hipError_t launch_lb(int lattice, int storage, const LBArgs &a, hipStream_t s);
 hipError_t launch_get_f(int lattice, int storage, const Geom &g, const void *A, double *f,
@@ -128,9 +176,8 @@ hipError_t launch_fill_u32(uint32_t *p, uint32_t value, int64_t count, hipStream
 hipError_t launch_fill_u64(uint64_t *p, uint64_t value, int64_t count, hipStream_t s);
 
 // launchers (particle_kernels.hip)
-hipError_t launch_foot_clear(const FootArgs &a, hipStream_t s);
+hipError_t launch_foot_clear(const FootArgs &a, int D, hipStream_t s);
 hipError_t launch_foot_paint(const FootArgs &a, int D, hipStream_t s);
-hipError_t launch_foot_bbox(const FootArgs &a, int D, hipStream_t s);
 hipError_t launch_force(const ForceArgs &a, hipStream_t s);
 hipError_t launch_cells(const CellArgs &a, hipStream_t s);
 hipError_t launch_dem(const CellArgs &a, hipStream_t s);

@@ -20,14 +20,9 @@
 // formulas with no fused multiply-add (the library is built with
 // -ffp-contract=off), so the result is reproducible bit for bit.
 #include "internal.h"
+#include "lb_shared.h"
 
 namespace lbimb {
-
-// ------------------------------------------------------------ storage
-template <int ST> struct Store;
-template <> struct Store<0> { using T = double; };
-template <> struct Store<1> { using T = float; };
-template <> struct Store<2> { using T = _Float16; };
 
 __device__ __forceinline__ double disp_periodic(double d, double L) {
     if (d > 0.5 * L) d = d - L;
@@ -94,52 +89,6 @@ __device__ __forceinline__ int solid_velocity(const LBArgs &a, int64_t n, int no
 #pragma unroll
     for (int d = 0; d < 3; d++) V[d] = d < L::D ? num[d] / den : 0.0;
     return total;
-}
-
-// c_i . u with the zero components of c_i dropped (exact for c in {-1,0,1}).
-template <class L, class R>
-__device__ __forceinline__ R cdot(int i, R ux, R uy, R uz) {
-    R s = R(0);
-    bool first = true;
-    if (L::cx[i] != 0) { s = L::cx[i] > 0 ? ux : -ux; first = false; }
-    if (L::cy[i] != 0) {
-        if (first) { s = L::cy[i] > 0 ? uy : -uy; first = false; }
-        else s = L::cy[i] > 0 ? s + uy : s - uy;
-    }
-    if (L::D == 3 && L::cz[i] != 0) {
-        if (first) { s = L::cz[i] > 0 ? uz : -uz; first = false; }
-        else s = L::cz[i] > 0 ? s + uz : s - uz;
-    }
-    return s;
-}
-
-// Sum over directions of c_ia * v_i, index order, zero terms dropped.
-template <class L, int AX, class R>
-__device__ __forceinline__ R cmoment(const R (&v)[L::Q]) {
-    R s = R(0);
-#pragma unroll
-    for (int i = 0; i < L::Q; i++) {
-        const int c = AX == 0 ? L::cx[i] : (AX == 1 ? L::cy[i] : L::cz[i]);
-        if (c > 0) s = s + v[i];
-        else if (c < 0) s = s - v[i];
-    }
-    return s;
-}
-
-// ------------------------------------------------------------- addressing
-// Every direction array has a base address that is uniform across the grid
-// (scalar registers); a node is a 32-bit byte offset from it when the array is
-// below 4 GiB, so loads and stores use the scalar-base + vector-offset form.
-template <class T, bool OFF32>
-__device__ __forceinline__ const T *at(const T *base, uint64_t idx) {
-    if (OFF32) return (const T *)((const char *)base + (uint32_t)((uint32_t)idx * (uint32_t)sizeof(T)));
-    return base + idx;
-}
-
-template <class T, bool OFF32>
-__device__ __forceinline__ T *at(T *base, uint64_t idx) {
-    if (OFF32) return (T *)((char *)base + (uint32_t)((uint32_t)idx * (uint32_t)sizeof(T)));
-    return base + idx;
 }
 
 // ------------------------------------------------------------- pull gather
@@ -265,68 +214,32 @@ __device__ __forceinline__ void collide_f64(const LBArgs &a, uint64_t n, int x, 
 template <class L, int ST, bool OFF32>
 __device__ __forceinline__ void collide_shifted(const LBArgs &a, uint64_t n, int x, int y, int z,
                                                 const float (&gg)[L::Q], int nown) {
-    float drho = gg[0];
-#pragma unroll
-    for (int i = 1; i < L::Q; i++) drho = drho + gg[i];
-    const float rho = 1.0f + drho;
-    const float jx = cmoment<L, 0>(gg), jy = cmoment<L, 1>(gg);
-    const float jz = L::D == 3 ? cmoment<L, 2>(gg) : 0.0f;
-    const float ux = jx / rho, uy = jy / rho, uz = L::D == 3 ? jz / rho : 0.0f;
-    float usq = ux * ux + uy * uy;
-    if (L::D == 3) usq = usq + uz * uz;
-    const float t15 = 1.5f * usq;
-    const float wf[3] = {(float)L::w[0], (float)L::w[1], (float)L::w[2]};
-    const float wrf[3] = {wf[0] * rho, wf[1] * rho, wf[2] * rho};
-    const float w3r[3] = {3.0f * wf[0] * rho, 3.0f * wf[1] * rho, 3.0f * wf[2] * rho};
     using T = typename Store<ST>::T;
     T *B = (T *)a.B;
     const uint64_t N = (uint64_t)a.g.N;
-    auto cu_of = [&](int i) { return i == 0 ? 0.0f : cdot<L>(i, ux, uy, uz); };
     auto put = [&](int i, float v) {
         T s;
         if (ST == 1) s = (T)v;
         else s = (T)(v * L::invw[L::wc[i]]);
         __builtin_nontemporal_store(s, at<T, OFF32>(B + (uint64_t)i * N, n));
     };
-    if (!__any(nown != 0)) {
-        const float ar = a.arel0f;
-#pragma unroll
-        for (int i = 0; i < L::Q; i++) {
-            const float cu = cu_of(i);
-            const float geq = wf[L::wc[i]] * (drho + rho * (3.0f * cu + 4.5f * cu * cu - t15));
-            put(i, gg[i] - ar * (gg[i] - geq) + w3r[L::wc[i]] * a.cgf[i]);
-        }
-        return;
-    }
-    if (nown > MAX_OWNERS) atomicOr(a.flags, FLAG_SLOT_OVERFLOW);
+    const bool wave_fluid = !__any(nown != 0);
+    float beta = 0.0f, ar = a.arel0f;
     double Vd[3] = {0.0, 0.0, 0.0};
     int total = 0;
-    if (nown != 0) total = solid_velocity<L>(a, (int64_t)n, nown, x, y, z, Vd);
-    const int cc = total < a.Smax ? total : a.Smax;
-    const float beta = nown != 0 ? (float)a.beta_tab[cc] : 0.0f;
-    const float ar = nown != 0 ? (float)a.arel_tab[cc] : a.arel0f;
-    const float V0 = (float)Vd[0], V1 = (float)Vd[1], V2 = (float)Vd[2];
-    float VV = V0 * V0 + V1 * V1;
-    if (L::D == 3) VV = VV + V2 * V2;
-    const float v15 = 1.5f * VV;
-    float mx = 0.0f, my = 0.0f, mz = 0.0f;
-#pragma unroll
-    for (int i = 0; i < L::Q; i++) {
-        const float cV = i == 0 ? 0.0f : cdot<L>(i, V0, V1, V2);
-        const float cu = cu_of(i);
-        const float pV = 3.0f * cV + 4.5f * cV * cV - v15;
-        const float pu = -3.0f * cu + 4.5f * cu * cu - t15;
-        const float Om = (gg[L::opp[i]] - gg[i]) + wrf[L::wc[i]] * (pV - pu);
-        const float geq = wf[L::wc[i]] * (drho + rho * (3.0f * cu + 4.5f * cu * cu - t15));
-        put(i, gg[i] - ar * (gg[i] - geq) + beta * Om + w3r[L::wc[i]] * a.cgf[i]);
-        if (L::cx[i] > 0) mx = mx + Om; else if (L::cx[i] < 0) mx = mx - Om;
-        if (L::cy[i] > 0) my = my + Om; else if (L::cy[i] < 0) my = my - Om;
-        if (L::D == 3) { if (L::cz[i] > 0) mz = mz + Om; else if (L::cz[i] < 0) mz = mz - Om; }
+    if (!wave_fluid && nown != 0) {
+        if (nown > MAX_OWNERS) atomicOr(a.flags, FLAG_SLOT_OVERFLOW);
+        total = solid_velocity<L>(a, (int64_t)n, nown, x, y, z, Vd);
+        const int cc = total < a.Smax ? total : a.Smax;
+        beta = (float)a.beta_tab[cc];
+        ar = (float)a.arel_tab[cc];
     }
+    float mom[3];
+    shifted_node<L>(gg, wave_fluid, beta, ar, (float)Vd[0], (float)Vd[1], (float)Vd[2], a.cgf, put, mom);
     if (nown != 0) {
-        a.q[n] = (double)(beta * mx);
-        a.q[N + n] = (double)(beta * my);
-        if (L::D == 3) a.q[2 * N + n] = (double)(beta * mz);
+        a.q[n] = (double)mom[0];
+        a.q[N + n] = (double)mom[1];
+        if (L::D == 3) a.q[2 * N + n] = (double)mom[2];
         a.ctot[n] = total;
     }
 }

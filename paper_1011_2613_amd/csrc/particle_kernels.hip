@@ -43,37 +43,6 @@ __device__ __forceinline__ void bbox(const Particles &P, int p, int D, int lo[3]
     }
 }
 
-__global__ void k_foot_bbox(FootArgs a, int D) {
-    const int p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= a.P.np) return;
-    int lo[3], hi[3];
-    bbox(a.P, p, D, lo, hi);
-    for (int d = 0; d < 3; d++) {
-        a.P.bb[d * a.P.np + p] = lo[d];
-        a.P.bb[(3 + d) * a.P.np + p] = hi[d];
-    }
-}
-
-// Zero the owner counts of every node painted in the previous step.
-__global__ __launch_bounds__(256) void k_foot_clear(FootArgs a) {
-    const int p = blockIdx.x;
-    const int P = a.P.np;
-    int lo[3], ext[3];
-    for (int d = 0; d < 3; d++) {
-        lo[d] = a.P.bb[d * P + p];
-        ext[d] = a.P.bb[(3 + d) * P + p] - lo[d] + 1;
-    }
-    const int total = ext[0] * ext[1] * ext[2];
-    for (int k = threadIdx.x; k < total; k += blockDim.x) {
-        const int cx = lo[0] + k % ext[0];
-        const int cy = lo[1] + (k / ext[0]) % ext[1];
-        const int cz = lo[2] + k / (ext[0] * ext[1]);
-        const int ix = wrapc(a.g, 0, cx), iy = wrapc(a.g, 1, cy), iz = wrapc(a.g, 2, cz);
-        if (iy < 0) continue;
-        a.nown[(int64_t)ix + (int64_t)a.g.nx * ((int64_t)iy + (int64_t)a.g.ny * iz)] = 0;
-    }
-}
-
 // Number of sub-cell samples of a node inside a particle: offsets
 // (k + 1/2)/S - 1/2 per axis from the node, inside test dx^2 + dy^2 (+ dz^2)
 // <= R^2 evaluated left to right, d0/d1/d2 the node-minus-centre displacement.
@@ -121,19 +90,48 @@ __device__ __forceinline__ int sample_count(double d0, double d1, double d2, dou
     return count;
 }
 
-// Node k of a bounding box with extents ext[] starting at lo[]; consecutive k
-// walk y first, then z, then x, so the lanes of a wavefront touch different
-// lattice rows (different words of the owner-count array).
-__device__ __forceinline__ void box_node(int k, const int lo[3], const int ext[3], int &cx, int &cy,
-                                         int &cz) {
-    cy = lo[1] + k % ext[1];
-    const int r = k / ext[1];
-    cz = lo[2] + r % ext[2];
-    cx = lo[0] + r / ext[2];
+// Unwrapped coordinate -> lattice coordinate.  A bounding box is narrower than
+// the periodic box, so one conditional shift suffices; -1 beyond a wall.
+__device__ __forceinline__ int wrap1(const Geom &g, int axis, int c) {
+    const int n = axis == 0 ? g.nx : (axis == 1 ? g.ny : g.nz);
+    if (axis == 1 && g.wall_y) return (c < 0 || c >= n) ? -1 : c;
+    return c < 0 ? c + n : (c >= n ? c - n : c);
 }
 
-// Paint the particle's footprint: sample count per node of the bounding box,
-// then claim an owner slot on every covered node.
+constexpr uint32_t LIST_COUNT_MASK = 1023u;
+
+__device__ __forceinline__ uint32_t list_entry(int count, int kx, int ky, int kz) {
+    return (uint32_t)count | ((uint32_t)kx << 10) | ((uint32_t)ky << 17) | ((uint32_t)kz << 24);
+}
+
+// Exclusive prefix sum over the threads of a workgroup (<= 256 threads);
+// `total` receives the sum.  Every thread of the workgroup must call it.
+__device__ __forceinline__ int block_scan(int v, int &total) {
+    __shared__ int wsum[4];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
+    int x = v;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const int y = __shfl_up(x, d, 64);
+        if (lane >= d) x += y;
+    }
+    if (lane == 63 || threadIdx.x == blockDim.x - 1) wsum[wave] = x;
+    __syncthreads();
+    int before = 0;
+    total = 0;
+    for (int w = 0; w < nw; w++) {
+        if (w < wave) before += wsum[w];
+        total += wsum[w];
+    }
+    __syncthreads();
+    return before + x - v;
+}
+
+// Footprint of one particle, one workgroup: an item is a bounding-box row
+// along x (3D) or a single node (2D).  Pass 1 counts an item's covered nodes,
+// a workgroup prefix sum gives each item its place in the particle's list,
+// pass 2 claims the owner slots and writes the list in item order, so the
+// list is the same on every run.
 template <int D, int S>
 __global__ __launch_bounds__(256) void k_foot_paint(FootArgs a) {
     const int p = blockIdx.x;
@@ -145,32 +143,88 @@ __global__ __launch_bounds__(256) void k_foot_paint(FootArgs a) {
             a.P.bb[d * P + p] = lo[d];
             a.P.bb[(3 + d) * P + p] = hi[d];
         }
-    const int ext[3] = {hi[0] - lo[0] + 1, hi[1] - lo[1] + 1, hi[2] - lo[2] + 1};
-    const int total = ext[0] * ext[1] * ext[2];
+    // A centre must lie in the box on periodic axes (integration keeps it
+    // there unless a particle moves a box length in one step) and be finite:
+    // otherwise the bounding box cannot be wrapped and the particle gets an
+    // empty footprint and an error flag.
+    bool placed = true;
+    for (int d = 0; d < D; d++) {
+        const double c = a.P.x[d * P + p];
+        const double L = d == 0 ? a.g.Lx : (d == 1 ? a.g.Ly : a.g.Lz);
+        placed = placed && ((d == 1 && a.g.wall_y) ? (c > -L && c < 2.0 * L) : (c >= 0.0 && c < L));
+    }
+    if (!placed && threadIdx.x == 0) atomicOr(a.flags, FLAG_NONFINITE);
+    const int ext0 = hi[0] - lo[0] + 1, ext1 = hi[1] - lo[1] + 1, ext2 = hi[2] - lo[2] + 1;
+    const int items = !placed ? 0 : (D == 3 ? ext1 * ext2 : ext0 * ext1);
     const double r = a.P.R[p];
     const double R2 = r * r;
     const double xp0 = a.P.x[p], xp1 = a.P.x[P + p], xp2 = D == 3 ? a.P.x[2 * P + p] : 0.0;
     const int64_t N = a.g.N;
-    for (int k = threadIdx.x; k < total; k += blockDim.x) {
-        int cx, cy, cz;
-        box_node(k, lo, ext, cx, cy, cz);
-        const int ix = wrapc(a.g, 0, cx), iy = wrapc(a.g, 1, cy);
-        const int iz = D == 3 ? wrapc(a.g, 2, cz) : 0;
-        if (iy < 0) continue;
-        const double d0 = ndisp(a.g, 0, ix, xp0);
-        const double d1 = ndisp(a.g, 1, iy, xp1);
-        const double d2 = D == 3 ? ndisp(a.g, 2, iz, xp2) : 0.0;
-        const int count = sample_count<D, S>(d0, d1, d2, R2);
-        if (count == 0) continue;
-        const int64_t n = (int64_t)ix + (int64_t)a.g.nx * ((int64_t)iy + (int64_t)a.g.ny * iz);
-        uint32_t *word = (uint32_t *)(a.nown + (n & ~(int64_t)3));
-        const int sh = 8 * (int)(n & 3);
-        const uint32_t old = atomicAdd(word, 1u << sh);
-        const int slot = (int)((old >> sh) & 0xffu);
-        if (slot < MAX_OWNERS)
-            a.slots[(int64_t)slot * N + n] = ((uint32_t)p << SLOT_COUNT_BITS) | (uint32_t)count;
-        else
-            atomicOr(a.flags, FLAG_SLOT_OVERFLOW);
+    uint32_t *list = a.P.list + (int64_t)p * a.P.list_cap;
+    int base = 0;
+    for (int it0 = 0; it0 < items; it0 += blockDim.x) {
+        const int item = it0 + threadIdx.x;
+        int kx0 = 0, kx1 = 0, ky = 0, kz = 0;
+        bool valid = false;
+        int iy = 0, iz = 0;
+        if (item < items) {
+            if (D == 3) { ky = item % ext1; kz = item / ext1; kx0 = 0; kx1 = ext0; }
+            else { kx0 = item % ext0; kx1 = kx0 + 1; ky = item / ext0; }
+            iy = wrap1(a.g, 1, lo[1] + ky);
+            iz = D == 3 ? wrap1(a.g, 2, lo[2] + kz) : 0;
+            valid = iy >= 0;
+        }
+        double d1 = 0.0, d2 = 0.0;
+        if (valid) {
+            d1 = ndisp(a.g, 1, iy, xp1);
+            d2 = D == 3 ? ndisp(a.g, 2, iz, xp2) : 0.0;
+        }
+        int ncov = 0;
+        if (valid)
+            for (int kx = kx0; kx < kx1; kx++) {
+                const int ix = wrap1(a.g, 0, lo[0] + kx);
+                ncov += sample_count<D, S>(ndisp(a.g, 0, ix, xp0), d1, d2, R2) > 0 ? 1 : 0;
+            }
+        int total;
+        int pos = base + block_scan(ncov, total);
+        if (valid && ncov > 0)
+            for (int kx = kx0; kx < kx1; kx++) {
+                const int ix = wrap1(a.g, 0, lo[0] + kx);
+                const int count = sample_count<D, S>(ndisp(a.g, 0, ix, xp0), d1, d2, R2);
+                if (count == 0) continue;
+                const int64_t n = (int64_t)ix + (int64_t)a.g.nx * ((int64_t)iy + (int64_t)a.g.ny * iz);
+                uint32_t *word = (uint32_t *)(a.nown + (n & ~(int64_t)3));
+                const int sh = 8 * (int)(n & 3);
+                const uint32_t old = atomicAdd(word, 1u << sh);
+                const int slot = (int)((old >> sh) & 0xffu);
+                if (slot < MAX_OWNERS)
+                    a.slots[(int64_t)slot * N + n] = ((uint32_t)p << SLOT_COUNT_BITS) | (uint32_t)count;
+                else
+                    atomicOr(a.flags, FLAG_SLOT_OVERFLOW);
+                if (pos < a.P.list_cap) list[pos] = list_entry(count, kx, ky, kz);
+                pos++;
+            }
+        base += total;
+    }
+    if (threadIdx.x == 0) {
+        if (base > a.P.list_cap) atomicOr(a.flags, FLAG_SLOT_OVERFLOW);
+        a.P.list_len[p] = base < a.P.list_cap ? base : a.P.list_cap;
+    }
+}
+
+// Zero the owner counts of the nodes listed in the previous step's footprint.
+__global__ __launch_bounds__(256) void k_foot_clear(FootArgs a, int D) {
+    const int p = blockIdx.x;
+    const int P = a.P.np;
+    const int len = a.P.list_len[p];
+    const int lo0 = a.P.bb[p], lo1 = a.P.bb[P + p], lo2 = a.P.bb[2 * P + p];
+    const uint32_t *list = a.P.list + (int64_t)p * a.P.list_cap;
+    for (int e = threadIdx.x; e < len; e += blockDim.x) {
+        const uint32_t v = list[e];
+        const int ix = wrap1(a.g, 0, lo0 + (int)((v >> 10) & 127u));
+        const int iy = wrap1(a.g, 1, lo1 + (int)((v >> 17) & 127u));
+        const int iz = D == 3 ? wrap1(a.g, 2, lo2 + (int)((v >> 24) & 127u)) : 0;
+        a.nown[(int64_t)ix + (int64_t)a.g.nx * ((int64_t)iy + (int64_t)a.g.ny * iz)] = 0;
     }
 }
 
@@ -199,83 +253,52 @@ __device__ __forceinline__ double shfl_xor_d(double v, int m) {
     return __shfl_xor(v, m, 64);
 }
 
-// One workgroup per particle.  A thread takes four nodes of the bounding box
-// at a time, recomputes the particle's own sample count on each (the same
-// exact test as the paint kernel), and loads q_n and the node's total count
-// for all four before using them, so the loads of a batch are in flight
-// together.  s_pn q_n and r_pn x (s_pn q_n) go into TwoSum accumulators; each
-// wavefront merges its lanes with butterfly shuffles and the first thread
-// merges the wavefronts in a fixed order.  F_p = -sum, T_p = -sum.
-template <int D, int S>
+// One workgroup per particle over its footprint list: each entry gives the
+// node and the particle's sample count there; q_n and the node's total count
+// come from the lattice kernel.  s_pn q_n and r_pn x (s_pn q_n) go into TwoSum
+// accumulators; each wavefront merges its lanes with butterfly shuffles and
+// the first thread merges the wavefronts in a fixed order.
+// F_p = -sum, T_p = -sum.
+template <int D>
 __global__ __launch_bounds__(256) void k_force(ForceArgs a) {
     __shared__ double part[4][12];
-    constexpr int U = 4;
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     const int nw = blockDim.x >> 6;
     const int p = blockIdx.x;
     const int P = a.P.np;
-    int lo[3], ext[3];
-    for (int d = 0; d < 3; d++) {
-        lo[d] = a.P.bb[d * P + p];
-        ext[d] = a.P.bb[(3 + d) * P + p] - lo[d] + 1;
-    }
-    const int total = ext[0] * ext[1] * ext[2];
-    const double r = a.P.R[p];
-    const double R2 = r * r;
+    const int len = a.P.list_len[p];
+    const int lo0 = a.P.bb[p], lo1 = a.P.bb[P + p], lo2 = a.P.bb[2 * P + p];
+    const uint32_t *list = a.P.list + (int64_t)p * a.P.list_cap;
     const double xp0 = a.P.x[p], xp1 = a.P.x[P + p], xp2 = D == 3 ? a.P.x[2 * P + p] : 0.0;
     const int64_t N = a.g.N;
     Acc F[3] = {{0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}};
     Acc T[3] = {{0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}};
-    for (int base = threadIdx.x; base < total; base += U * blockDim.x) {
-        int cnt[U];
-        int64_t nn[U];
-        double rr[U][3];
-#pragma unroll
-        for (int u = 0; u < U; u++) {
-            const int k = base + u * blockDim.x;
-            cnt[u] = 0;
-            nn[u] = 0;
-            rr[u][0] = rr[u][1] = rr[u][2] = 0.0;
-            if (k >= total) continue;
-            int cx, cy, cz;
-            box_node(k, lo, ext, cx, cy, cz);
-            const int ix = wrapc(a.g, 0, cx), iy = wrapc(a.g, 1, cy);
-            const int iz = D == 3 ? wrapc(a.g, 2, cz) : 0;
-            if (iy < 0) continue;
-            rr[u][0] = ndisp(a.g, 0, ix, xp0);
-            rr[u][1] = ndisp(a.g, 1, iy, xp1);
-            rr[u][2] = D == 3 ? ndisp(a.g, 2, iz, xp2) : 0.0;
-            cnt[u] = sample_count<D, S>(rr[u][0], rr[u][1], rr[u][2], R2);
-            if (cnt[u] > 0) nn[u] = (int64_t)ix + (int64_t)a.g.nx * ((int64_t)iy + (int64_t)a.g.ny * iz);
-        }
-        double q0[U], q1[U], q2[U];
-        int tot[U];
-#pragma unroll
-        for (int u = 0; u < U; u++) {
-            q0[u] = a.q[nn[u]];
-            q1[u] = a.q[N + nn[u]];
-            q2[u] = D == 3 ? a.q[2 * N + nn[u]] : 0.0;
-            tot[u] = a.ctot[nn[u]];
-        }
-#pragma unroll
-        for (int u = 0; u < U; u++) {
-            if (cnt[u] == 0) continue;
-            const double sh = (double)cnt[u] / (double)tot[u];
-            const double t0 = sh * q0[u], t1 = sh * q1[u];
-            const double rx = rr[u][0], ry = rr[u][1];
-            acc_add(F[0], t0);
-            acc_add(F[1], t1);
-            if (D == 3) {
-                const double t2 = sh * q2[u];
-                const double rz = rr[u][2];
-                acc_add(F[2], t2);
-                acc_add(T[0], ry * t2 - rz * t1);
-                acc_add(T[1], rz * t0 - rx * t2);
-                acc_add(T[2], rx * t1 - ry * t0);
-            } else {
-                acc_add(T[2], rx * t1 - ry * t0);
-            }
+    for (int e = threadIdx.x; e < len; e += blockDim.x) {
+        const uint32_t v = list[e];
+        const int cnt = (int)(v & LIST_COUNT_MASK);
+        const int ix = wrap1(a.g, 0, lo0 + (int)((v >> 10) & 127u));
+        const int iy = wrap1(a.g, 1, lo1 + (int)((v >> 17) & 127u));
+        const int iz = D == 3 ? wrap1(a.g, 2, lo2 + (int)((v >> 24) & 127u)) : 0;
+        const int64_t n = (int64_t)ix + (int64_t)a.g.nx * ((int64_t)iy + (int64_t)a.g.ny * iz);
+        const double q0 = a.q[n], q1 = a.q[N + n];
+        const double q2 = D == 3 ? a.q[2 * N + n] : 0.0;
+        const int tot = a.ctot[n];
+        const double sh = (double)cnt / (double)tot;
+        const double t0 = sh * q0, t1 = sh * q1;
+        const double rx = ndisp(a.g, 0, ix, xp0);
+        const double ry = ndisp(a.g, 1, iy, xp1);
+        acc_add(F[0], t0);
+        acc_add(F[1], t1);
+        if (D == 3) {
+            const double t2 = sh * q2;
+            const double rz = ndisp(a.g, 2, iz, xp2);
+            acc_add(F[2], t2);
+            acc_add(T[0], ry * t2 - rz * t1);
+            acc_add(T[1], rz * t0 - rx * t2);
+            acc_add(T[2], rx * t1 - ry * t0);
+        } else {
+            acc_add(T[2], rx * t1 - ry * t0);
         }
     }
 #pragma unroll
@@ -496,15 +519,10 @@ __global__ void k_integrate(CellArgs a) {
 // ---------------------------------------------------------------- launchers
 static unsigned blocks_for(int n, int per) { return (unsigned)((n + per - 1) / per); }
 
-hipError_t launch_foot_bbox(const FootArgs &a, int D, hipStream_t s) {
+hipError_t launch_foot_clear(const FootArgs &a, int D, hipStream_t s) {
     if (a.P.np == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_foot_bbox, dim3(blocks_for(a.P.np, 256)), dim3(256), 0, s, a, D);
-    return hipGetLastError();
-}
-
-hipError_t launch_foot_clear(const FootArgs &a, hipStream_t s) {
-    if (a.P.np == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_foot_clear, dim3((unsigned)a.P.np), dim3(a.g.nz == 1 ? 128 : 256), 0, s, a);
+    if (D == 2) hipLaunchKernelGGL(k_foot_clear, dim3((unsigned)a.P.np), dim3(64), 0, s, a, D);
+    else hipLaunchKernelGGL(k_foot_clear, dim3((unsigned)a.P.np), dim3(128), 0, s, a, D);
     return hipGetLastError();
 }
 
@@ -526,28 +544,14 @@ static hipError_t paint_s(const FootArgs &a, hipStream_t s, int block) {
 
 hipError_t launch_foot_paint(const FootArgs &a, int D, hipStream_t s) {
     if (a.P.np == 0) return hipSuccess;
-    return D == 2 ? paint_s<2>(a, s, 128) : paint_s<3>(a, s, 256);
-}
-
-template <int D>
-static hipError_t force_s(const ForceArgs &a, hipStream_t s, int block) {
-    const dim3 g((unsigned)a.P.np), b((unsigned)block);
-    switch (a.S) {
-        case 1: hipLaunchKernelGGL((k_force<D, 1>), g, b, 0, s, a); break;
-        case 2: hipLaunchKernelGGL((k_force<D, 2>), g, b, 0, s, a); break;
-        case 3: hipLaunchKernelGGL((k_force<D, 3>), g, b, 0, s, a); break;
-        case 4: hipLaunchKernelGGL((k_force<D, 4>), g, b, 0, s, a); break;
-        case 5: hipLaunchKernelGGL((k_force<D, 5>), g, b, 0, s, a); break;
-        case 6: hipLaunchKernelGGL((k_force<D, 6>), g, b, 0, s, a); break;
-        case 7: hipLaunchKernelGGL((k_force<D, 7>), g, b, 0, s, a); break;
-        default: hipLaunchKernelGGL((k_force<D, 8>), g, b, 0, s, a); break;
-    }
-    return hipGetLastError();
+    return D == 2 ? paint_s<2>(a, s, 128) : paint_s<3>(a, s, 128);
 }
 
 hipError_t launch_force(const ForceArgs &a, hipStream_t s) {
     if (a.P.np == 0) return hipSuccess;
-    return a.D == 2 ? force_s<2>(a, s, 64) : force_s<3>(a, s, 256);
+    if (a.D == 2) hipLaunchKernelGGL(k_force<2>, dim3((unsigned)a.P.np), dim3(64), 0, s, a);
+    else hipLaunchKernelGGL(k_force<3>, dim3((unsigned)a.P.np), dim3(128), 0, s, a);
+    return hipGetLastError();
 }
 
 hipError_t launch_cells(const CellArgs &a, hipStream_t s) {

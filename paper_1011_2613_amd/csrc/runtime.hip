@@ -36,6 +36,9 @@ struct Layout {
     int64_t cell_budget;
     size_t off_fA, off_fB, off_nown, off_slots, off_q, off_ctot, off_beta, off_arel;
     size_t off_x, off_v, off_w, off_R, off_m, off_I, off_fixed, off_Fh, off_Th, off_Fc, off_bb;
+    size_t off_list, off_list_len;
+    int list_cap;
+    double rmax;
     size_t off_cc, off_cid, off_flags, total;
 };
 
@@ -52,6 +55,7 @@ int validate(const lbm_config *c, std::string &msg) {
     if (c->max_particles < 0 || c->max_particles > LBM_MAX_PARTICLES) { msg = "max_particles out of range"; return LBM_E_INVALID; }
     if (!(c->restitution > 0.0 && c->restitution <= 1.0)) { msg = "restitution must be in (0, 1]"; return LBM_E_INVALID; }
     if (!(c->kn >= 0.0)) { msg = "kn must be >= 0"; return LBM_E_INVALID; }
+    if (!(c->max_radius <= 62.0) || std::isnan(c->max_radius)) { msg = "max_radius must be <= 62"; return LBM_E_INVALID; }
     for (int a = 0; a < 3; a++)
         if (!std::isfinite(c->fluid_force[a]) || !std::isfinite(c->particle_accel[a])) {
             msg = "non-finite force"; return LBM_E_INVALID;
@@ -90,6 +94,12 @@ Layout make_layout(const lbm_config *c) {
     L.off_Th = take(3 * P * 8);
     L.off_Fc = take(3 * P * 8);
     L.off_bb = take(6 * P * 4);
+    // footprint list: every node of the bounding box of the largest particle
+    L.rmax = c->max_radius > 0.0 ? c->max_radius : 8.0;
+    const int ext = (int)std::floor(2.0 * L.rmax + 1.0) + 1;
+    L.list_cap = L.D == 2 ? ext * ext : ext * ext * ext;
+    L.off_list = take(P * (size_t)L.list_cap * 4);
+    L.off_list_len = take(P * 4);
     L.off_cc = take((size_t)L.cell_budget * 4);
     L.off_cid = take((size_t)L.cell_budget * CELL_CAP * 4);
     L.off_flags = take(64);
@@ -163,6 +173,9 @@ Particles particles(lbm_ctx *c) {
     P.Th = wsp<double>(c, c->L.off_Th);
     P.Fc = wsp<double>(c, c->L.off_Fc);
     P.bb = wsp<int>(c, c->L.off_bb);
+    P.list = wsp<uint32_t>(c, c->L.off_list);
+    P.list_len = wsp<int>(c, c->L.off_list_len);
+    P.list_cap = c->L.list_cap;
     P.np = c->np;
     return P;
 }
@@ -250,7 +263,7 @@ hipError_t enqueue_step(lbm_ctx *c, int from, hipStream_t s) {
     if (c->np > 0) {
         FootArgs fa = foot_args(c);
         phase_begin(c, 0, s);
-        if ((e = launch_foot_clear(fa, s)) != hipSuccess) return e;
+        if ((e = launch_foot_clear(fa, c->L.D, s)) != hipSuccess) return e;
         if ((e = launch_foot_paint(fa, c->L.D, s)) != hipSuccess) return e;
         phase_end(c, s);
     }
@@ -263,7 +276,6 @@ hipError_t enqueue_step(lbm_ctx *c, int from, hipStream_t s) {
         fo.g = c->g;
         fo.ctot = wsp<int>(c, c->L.off_ctot);
         fo.q = wsp<double>(c, c->L.off_q);
-        fo.S = c->cfg.eps_samples;
         fo.D = c->L.D;
         phase_begin(c, 2, s);
         if ((e = launch_force(fo, s)) != hipSuccess) return e;
@@ -314,7 +326,7 @@ int check_flags(lbm_ctx *c) {
         return fail(c, LBM_E_CELL_OVERFLOW, "a DEM cell holds more than %d particles", CELL_CAP);
     if (h[0] & FLAG_CONTACT_OVERFLOW)
         return fail(c, LBM_E_CONTACT_OVERFLOW, "a particle has more than %d contacts", MAX_CONTACTS);
-    if (h[0] & FLAG_NONFINITE) return fail(c, LBM_E_NONFINITE, "non-finite value in the state");
+    if (h[0] & FLAG_NONFINITE) return fail(c, LBM_E_NONFINITE, "non-finite value in the state or a particle outside the box");
     return LBM_OK;
 }
 
@@ -356,7 +368,7 @@ const char *lbm_error_string(int code) {
         case LBM_E_INVALID: return "invalid argument";
         case LBM_E_NOMEM: return "workspace too small";
         case LBM_E_HIP: return "HIP runtime error";
-        case LBM_E_NONFINITE: return "non-finite value in the state";
+        case LBM_E_NONFINITE: return "non-finite value in the state or a particle outside the box";
         case LBM_E_SLOT_OVERFLOW: return "too many particles cover one node";
         case LBM_E_STATE: return "call out of order";
         case LBM_E_IO: return "file error";
@@ -496,6 +508,7 @@ int lbm_set_particles(lbm_ctx *c, int64_t n, const double *pos, const double *ve
     for (int p = 0; p < P; p++) {
         const double r = radius[p];
         if (!(r > 0.0) || !std::isfinite(r)) return fail(c, LBM_E_INVALID, "particle %d: radius must be > 0", p);
+        if (r > c->L.rmax) return fail(c, LBM_E_INVALID, "particle %d: radius %g above max_radius %g", p, r, c->L.rmax);
         if (!(rho_s[p] > 0.0) || !std::isfinite(rho_s[p])) return fail(c, LBM_E_INVALID, "particle %d: density must be > 0", p);
         for (int a = 0; a < D; a++) {
             if (!std::isfinite(pos[3 * p + a]) || !std::isfinite(vel[3 * p + a]))
@@ -609,7 +622,7 @@ int lbm_set_particles(lbm_ctx *c, int64_t n, const double *pos, const double *ve
     HIPCHK(c, launch_fill_u32(wsp<uint32_t>(c, c->L.off_Fh), 0u, (int64_t)(3 * np * 2), c->stream));
     HIPCHK(c, launch_fill_u32(wsp<uint32_t>(c, c->L.off_Th), 0u, (int64_t)(3 * np * 2), c->stream));
     HIPCHK(c, launch_fill_u32(wsp<uint32_t>(c, c->L.off_Fc), 0u, (int64_t)(3 * np * 2), c->stream));
-    HIPCHK(c, launch_foot_bbox(foot_args(c), D, c->stream));
+    HIPCHK(c, launch_fill_u32(wsp<uint32_t>(c, c->L.off_list_len), 0u, (int64_t)np, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     c->particles_set = true;
     return LBM_OK;
@@ -854,7 +867,7 @@ int lbm_load(lbm_ctx *c, const char *path) {
     c->t = t;
     c->particles_set = true;
     HIPCHK(c, launch_fill_u32(wsp<uint32_t>(c, c->L.off_nown), 0u, (int64_t)((c->L.N + 3) / 4), c->stream));
-    HIPCHK(c, launch_foot_bbox(foot_args(c), c->L.D, c->stream));
+    HIPCHK(c, launch_fill_u32(wsp<uint32_t>(c, c->L.off_list_len), 0u, (int64_t)std::max(np, 1), c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     return LBM_OK;
 }

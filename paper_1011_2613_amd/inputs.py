@@ -136,6 +136,21 @@ def perturbation(Q, N, amplitude, seed):
     return (uniform(seed, 0, Q * N).reshape(Q, N) * 2.0 - 1.0) * amplitude
 
 
+def mlp_initial_params(seed, sizes=(40, 128, 128, 128, 1)):
+    """Seeded Kaiming-uniform weights (bound sqrt(6 / fan_in)) and zero biases
+    of the drag-closure MLP, as [[W, b], ...] with W [fan_out, fan_in]; the
+    values are binary32-representable."""
+    params = []
+    pos = 0
+    for fin, fout in zip(sizes[:-1], sizes[1:]):
+        bound = math.sqrt(6.0 / fin)
+        u = uniform(seed, pos, fin * fout)
+        pos += fin * fout
+        W = ((u * 2.0 - 1.0) * bound).reshape(fout, fin).astype(np.float32).astype(np.float64)
+        params.append([W, np.zeros(fout)])
+    return params
+
+
 def solid_fraction_count(dim, box, radius, phi, wall_y=False):
     """Particle count for a target solid fraction of the fluid box."""
     vol = float(np.prod(box[:dim]))
