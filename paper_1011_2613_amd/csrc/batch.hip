@@ -62,7 +62,7 @@ __device__ __forceinline__ void batch_tile(const BatchArgs &a, const BatchBox &b
         const float ar = cnt != 0 ? arel_t[cc] : bx.arel0f;
         auto put = [&](int i, float v) { __builtin_nontemporal_store(v, &B[(uint64_t)i * N + n]); };
         float mom[3];
-        shifted_node<L>(gg, wave_fluid, beta, ar, 0.0f, 0.0f, 0.0f, bx.cgf, put, mom);
+        shifted_node<L, false>(gg, wave_fluid, beta, ar, 0.0f, 0.0f, 0.0f, bx.cgf, put, mom);
         if (cnt != 0) {
             const uint64_t m = (uint64_t)bx.noff + n;
             a.q[m] = mom[0];

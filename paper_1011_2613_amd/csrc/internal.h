@@ -104,6 +104,7 @@ struct ForceArgs {
     Geom g;
     const int *ctot;
     const double *q;
+    uint8_t *nown;  // owner counts, zeroed at the listed nodes once read
     int D;
 };
 
@@ -176,9 +177,9 @@ hipError_t launch_fill_u32(uint32_t *p, uint32_t value, int64_t count, hipStream
 hipError_t launch_fill_u64(uint64_t *p, uint64_t value, int64_t count, hipStream_t s);
 
 // launchers (particle_kernels.hip)
-hipError_t launch_foot_clear(const FootArgs &a, int D, hipStream_t s);
 hipError_t launch_foot_paint(const FootArgs &a, int D, hipStream_t s);
 hipError_t launch_force(const ForceArgs &a, hipStream_t s);
+hipError_t launch_list_q(const ForceArgs &a, double *out, hipStream_t s);
 hipError_t launch_cells(const CellArgs &a, hipStream_t s);
 hipError_t launch_dem(const CellArgs &a, hipStream_t s);
 hipError_t launch_integrate(const CellArgs &a, hipStream_t s);

@@ -94,7 +94,10 @@ __device__ __forceinline__ int solid_velocity(const LBArgs &a, int64_t n, int no
 // ------------------------------------------------------------- pull gather
 // f_i(x) = A_i(x - c_i), or A_opp(i)(x) when x - c_i lies beyond a wall.  All
 // threads of a block share y and z (the grid is one block row per lattice row),
-// so the bounce-back test and the direction base are uniform per block.
+// so the bounce-back test, the row offsets of the 9 source rows and every
+// direction's base address are uniform per block (scalar registers); off the
+// wall rows a source address is then one vector add: the lane's x, x - 1 or
+// x + 1 (wrapped) byte offset plus the direction's uniform row offset.
 template <class L, class T, bool OFF32>
 __device__ __forceinline__ void gather(const T *__restrict__ A, const Geom &g, int x, int y, int z,
                                        uint64_t n, T (&f)[L::Q]) {
@@ -111,6 +114,19 @@ __device__ __forceinline__ void gather(const T *__restrict__ A, const Geom &g, i
         if (yp >= ny) yp = 0;
     }
     const int zm = z == 0 ? nz - 1 : z - 1, zp = z == nz - 1 ? 0 : z + 1;
+    if (OFF32 && !lo && !hi) {
+        const uint32_t sz = (uint32_t)sizeof(T);
+        const uint32_t ox[3] = {(uint32_t)x * sz, (uint32_t)xm * sz, (uint32_t)xp * sz};
+#pragma unroll
+        for (int i = 0; i < L::Q; i++) {
+            const int sy = L::cy[i] == 0 ? y : (L::cy[i] > 0 ? ym : yp);
+            const int szz = L::cz[i] == 0 ? z : (L::cz[i] > 0 ? zm : zp);
+            const uint32_t row = ((uint32_t)sy + (uint32_t)ny * (uint32_t)szz) * (uint32_t)nx * sz;
+            const uint32_t xo = ox[L::cx[i] == 0 ? 0 : (L::cx[i] > 0 ? 1 : 2)];
+            f[i] = *(const T *)((const char *)(A + (uint64_t)i * N) + (xo + row));
+        }
+        return;
+    }
 #pragma unroll
     for (int i = 0; i < L::Q; i++) {
         const int sx = L::cx[i] == 0 ? x : (L::cx[i] > 0 ? xm : xp);
@@ -217,12 +233,7 @@ __device__ __forceinline__ void collide_shifted(const LBArgs &a, uint64_t n, int
     using T = typename Store<ST>::T;
     T *B = (T *)a.B;
     const uint64_t N = (uint64_t)a.g.N;
-    auto put = [&](int i, float v) {
-        T s;
-        if (ST == 1) s = (T)v;
-        else s = (T)(v * L::invw[L::wc[i]]);
-        __builtin_nontemporal_store(s, at<T, OFF32>(B + (uint64_t)i * N, n));
-    };
+    auto put = [&](int i, float v) { __builtin_nontemporal_store((T)v, at<T, OFF32>(B + (uint64_t)i * N, n)); };
     const bool wave_fluid = !__any(nown != 0);
     float beta = 0.0f, ar = a.arel0f;
     double Vd[3] = {0.0, 0.0, 0.0};
@@ -235,7 +246,7 @@ __device__ __forceinline__ void collide_shifted(const LBArgs &a, uint64_t n, int
         ar = (float)a.arel_tab[cc];
     }
     float mom[3];
-    shifted_node<L>(gg, wave_fluid, beta, ar, (float)Vd[0], (float)Vd[1], (float)Vd[2], a.cgf, put, mom);
+    shifted_node<L, ST == 2>(gg, wave_fluid, beta, ar, (float)Vd[0], (float)Vd[1], (float)Vd[2], a.cgf, put, mom);
     if (nown != 0) {
         a.q[n] = (double)mom[0];
         a.q[N + n] = (double)mom[1];
@@ -260,11 +271,11 @@ __global__ __launch_bounds__(256) void k_lb(LBArgs a) {
         for (int i = 0; i < L::Q; i++) fd[i] = (double)f[i];
         collide_f64<L, OFF32>(a, n, x, y, z, fd, nown);
     } else {
+        // FP32 storage holds g_i, FP16 storage g_i / w_i; the collision works
+        // in the storage unit
         float gg[L::Q];
-        const float wf[3] = {(float)L::w[0], (float)L::w[1], (float)L::w[2]};
 #pragma unroll
-        for (int i = 0; i < L::Q; i++)
-            gg[i] = ST == 1 ? (float)f[i] : wf[L::wc[i]] * (float)f[i];
+        for (int i = 0; i < L::Q; i++) gg[i] = (float)f[i];
         collide_shifted<L, ST, OFF32>(a, n, x, y, z, gg, nown);
     }
 }

@@ -127,11 +127,11 @@ __device__ __forceinline__ int block_scan(int v, int &total) {
     return before + x - v;
 }
 
-// Footprint of one particle, one workgroup: an item is a bounding-box row
-// along x (3D) or a single node (2D).  Pass 1 counts an item's covered nodes,
-// a workgroup prefix sum gives each item its place in the particle's list,
-// pass 2 claims the owner slots and writes the list in item order, so the
-// list is the same on every run.
+// Footprint of one particle, one workgroup, one bounding-box node per thread
+// and pass: the thread computes the node's sample count once, a workgroup
+// prefix sum over "covered" gives its place in the particle's list (node
+// order x fastest, so the list is the same on every run), and the thread
+// claims an owner slot and writes its list entry.
 template <int D, int S>
 __global__ __launch_bounds__(256) void k_foot_paint(FootArgs a) {
     const int p = blockIdx.x;
@@ -154,77 +154,52 @@ __global__ __launch_bounds__(256) void k_foot_paint(FootArgs a) {
         placed = placed && ((d == 1 && a.g.wall_y) ? (c > -L && c < 2.0 * L) : (c >= 0.0 && c < L));
     }
     if (!placed && threadIdx.x == 0) atomicOr(a.flags, FLAG_NONFINITE);
-    const int ext0 = hi[0] - lo[0] + 1, ext1 = hi[1] - lo[1] + 1, ext2 = hi[2] - lo[2] + 1;
-    const int items = !placed ? 0 : (D == 3 ? ext1 * ext2 : ext0 * ext1);
+    const int ext0 = hi[0] - lo[0] + 1, ext1 = hi[1] - lo[1] + 1;
+    const int ext2 = D == 3 ? hi[2] - lo[2] + 1 : 1;
+    const int items = placed ? ext0 * ext1 * ext2 : 0;
     const double r = a.P.R[p];
     const double R2 = r * r;
     const double xp0 = a.P.x[p], xp1 = a.P.x[P + p], xp2 = D == 3 ? a.P.x[2 * P + p] : 0.0;
     const int64_t N = a.g.N;
-    uint32_t *list = a.P.list + (int64_t)p * a.P.list_cap;
+    const int cap = a.P.list_cap;
+    uint32_t *list = a.P.list + (int64_t)p * cap;
     int base = 0;
     for (int it0 = 0; it0 < items; it0 += blockDim.x) {
         const int item = it0 + threadIdx.x;
-        int kx0 = 0, kx1 = 0, ky = 0, kz = 0;
-        bool valid = false;
-        int iy = 0, iz = 0;
+        int count = 0, kx = 0, ky = 0, kz = 0;
+        int64_t n = 0;
         if (item < items) {
-            if (D == 3) { ky = item % ext1; kz = item / ext1; kx0 = 0; kx1 = ext0; }
-            else { kx0 = item % ext0; kx1 = kx0 + 1; ky = item / ext0; }
-            iy = wrap1(a.g, 1, lo[1] + ky);
-            iz = D == 3 ? wrap1(a.g, 2, lo[2] + kz) : 0;
-            valid = iy >= 0;
-        }
-        double d1 = 0.0, d2 = 0.0;
-        if (valid) {
-            d1 = ndisp(a.g, 1, iy, xp1);
-            d2 = D == 3 ? ndisp(a.g, 2, iz, xp2) : 0.0;
-        }
-        int ncov = 0;
-        if (valid)
-            for (int kx = kx0; kx < kx1; kx++) {
+            kx = item % ext0;
+            const int rest = item / ext0;
+            ky = rest % ext1;
+            kz = rest / ext1;
+            const int iy = wrap1(a.g, 1, lo[1] + ky);
+            if (iy >= 0) {
                 const int ix = wrap1(a.g, 0, lo[0] + kx);
-                ncov += sample_count<D, S>(ndisp(a.g, 0, ix, xp0), d1, d2, R2) > 0 ? 1 : 0;
+                const int iz = D == 3 ? wrap1(a.g, 2, lo[2] + kz) : 0;
+                count = sample_count<D, S>(ndisp(a.g, 0, ix, xp0), ndisp(a.g, 1, iy, xp1),
+                                           D == 3 ? ndisp(a.g, 2, iz, xp2) : 0.0, R2);
+                n = (int64_t)ix + (int64_t)a.g.nx * ((int64_t)iy + (int64_t)a.g.ny * iz);
             }
+        }
         int total;
-        int pos = base + block_scan(ncov, total);
-        if (valid && ncov > 0)
-            for (int kx = kx0; kx < kx1; kx++) {
-                const int ix = wrap1(a.g, 0, lo[0] + kx);
-                const int count = sample_count<D, S>(ndisp(a.g, 0, ix, xp0), d1, d2, R2);
-                if (count == 0) continue;
-                const int64_t n = (int64_t)ix + (int64_t)a.g.nx * ((int64_t)iy + (int64_t)a.g.ny * iz);
-                uint32_t *word = (uint32_t *)(a.nown + (n & ~(int64_t)3));
-                const int sh = 8 * (int)(n & 3);
-                const uint32_t old = atomicAdd(word, 1u << sh);
-                const int slot = (int)((old >> sh) & 0xffu);
-                if (slot < MAX_OWNERS)
-                    a.slots[(int64_t)slot * N + n] = ((uint32_t)p << SLOT_COUNT_BITS) | (uint32_t)count;
-                else
-                    atomicOr(a.flags, FLAG_SLOT_OVERFLOW);
-                if (pos < a.P.list_cap) list[pos] = list_entry(count, kx, ky, kz);
-                pos++;
-            }
+        const int pos = base + block_scan(count > 0 ? 1 : 0, total);
+        if (count > 0) {
+            uint32_t *word = (uint32_t *)(a.nown + (n & ~(int64_t)3));
+            const int sh = 8 * (int)(n & 3);
+            const uint32_t old = atomicAdd(word, 1u << sh);
+            const int slot = (int)((old >> sh) & 0xffu);
+            if (slot < MAX_OWNERS)
+                a.slots[(int64_t)slot * N + n] = ((uint32_t)p << SLOT_COUNT_BITS) | (uint32_t)count;
+            else
+                atomicOr(a.flags, FLAG_SLOT_OVERFLOW);
+            if (pos < cap) list[pos] = list_entry(count, kx, ky, kz);
+        }
         base += total;
     }
     if (threadIdx.x == 0) {
-        if (base > a.P.list_cap) atomicOr(a.flags, FLAG_SLOT_OVERFLOW);
-        a.P.list_len[p] = base < a.P.list_cap ? base : a.P.list_cap;
-    }
-}
-
-// Zero the owner counts of the nodes listed in the previous step's footprint.
-__global__ __launch_bounds__(256) void k_foot_clear(FootArgs a, int D) {
-    const int p = blockIdx.x;
-    const int P = a.P.np;
-    const int len = a.P.list_len[p];
-    const int lo0 = a.P.bb[p], lo1 = a.P.bb[P + p], lo2 = a.P.bb[2 * P + p];
-    const uint32_t *list = a.P.list + (int64_t)p * a.P.list_cap;
-    for (int e = threadIdx.x; e < len; e += blockDim.x) {
-        const uint32_t v = list[e];
-        const int ix = wrap1(a.g, 0, lo0 + (int)((v >> 10) & 127u));
-        const int iy = wrap1(a.g, 1, lo1 + (int)((v >> 17) & 127u));
-        const int iz = D == 3 ? wrap1(a.g, 2, lo2 + (int)((v >> 24) & 127u)) : 0;
-        a.nown[(int64_t)ix + (int64_t)a.g.nx * ((int64_t)iy + (int64_t)a.g.ny * iz)] = 0;
+        if (base > cap) atomicOr(a.flags, FLAG_SLOT_OVERFLOW);
+        a.P.list_len[p] = base < cap ? base : cap;
     }
 }
 
@@ -255,7 +230,8 @@ __device__ __forceinline__ double shfl_xor_d(double v, int m) {
 
 // One workgroup per particle over its footprint list: each entry gives the
 // node and the particle's sample count there; q_n and the node's total count
-// come from the lattice kernel.  s_pn q_n and r_pn x (s_pn q_n) go into TwoSum
+// come from the lattice kernel.  The kernel also zeroes the owner count of
+// every listed node (the footprint of the next step starts from zero counts).  s_pn q_n and r_pn x (s_pn q_n) go into TwoSum
 // accumulators; each wavefront merges its lanes with butterfly shuffles and
 // the first thread merges the wavefronts in a fixed order.
 // F_p = -sum, T_p = -sum.
@@ -274,31 +250,57 @@ __global__ __launch_bounds__(256) void k_force(ForceArgs a) {
     const int64_t N = a.g.N;
     Acc F[3] = {{0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}};
     Acc T[3] = {{0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}};
-    for (int e = threadIdx.x; e < len; e += blockDim.x) {
-        const uint32_t v = list[e];
-        const int cnt = (int)(v & LIST_COUNT_MASK);
-        const int ix = wrap1(a.g, 0, lo0 + (int)((v >> 10) & 127u));
-        const int iy = wrap1(a.g, 1, lo1 + (int)((v >> 17) & 127u));
-        const int iz = D == 3 ? wrap1(a.g, 2, lo2 + (int)((v >> 24) & 127u)) : 0;
-        const int64_t n = (int64_t)ix + (int64_t)a.g.nx * ((int64_t)iy + (int64_t)a.g.ny * iz);
-        const double q0 = a.q[n], q1 = a.q[N + n];
-        const double q2 = D == 3 ? a.q[2 * N + n] : 0.0;
-        const int tot = a.ctot[n];
-        const double sh = (double)cnt / (double)tot;
-        const double t0 = sh * q0, t1 = sh * q1;
-        const double rx = ndisp(a.g, 0, ix, xp0);
-        const double ry = ndisp(a.g, 1, iy, xp1);
-        acc_add(F[0], t0);
-        acc_add(F[1], t1);
-        if (D == 3) {
-            const double t2 = sh * q2;
-            const double rz = ndisp(a.g, 2, iz, xp2);
-            acc_add(F[2], t2);
-            acc_add(T[0], ry * t2 - rz * t1);
-            acc_add(T[1], rz * t0 - rx * t2);
-            acc_add(T[2], rx * t1 - ry * t0);
-        } else {
-            acc_add(T[2], rx * t1 - ry * t0);
+    // UN entries per thread per round: all list and q loads of a round are
+    // issued before the first accumulation, so a round costs two memory
+    // latencies instead of two per entry.
+    constexpr int UN = 4;
+    for (int e0 = 0; e0 < len; e0 += UN * (int)blockDim.x) {
+        uint32_t v[UN];
+#pragma unroll
+        for (int u = 0; u < UN; u++) {
+            const int e = e0 + u * (int)blockDim.x + (int)threadIdx.x;
+            v[u] = e < len ? list[e] : 0u;
+        }
+        double q0[UN], q1[UN], q2[UN];
+        int tot[UN], ix[UN], iy[UN], iz[UN];
+#pragma unroll
+        for (int u = 0; u < UN; u++) {
+            ix[u] = wrap1(a.g, 0, lo0 + (int)((v[u] >> 10) & 127u));
+            iy[u] = wrap1(a.g, 1, lo1 + (int)((v[u] >> 17) & 127u));
+            iz[u] = D == 3 ? wrap1(a.g, 2, lo2 + (int)((v[u] >> 24) & 127u)) : 0;
+            q0[u] = q1[u] = q2[u] = 0.0;
+            tot[u] = 1;
+            if (v[u] != 0u) {
+                const int64_t n = (int64_t)ix[u] + (int64_t)a.g.nx * ((int64_t)iy[u] + (int64_t)a.g.ny * iz[u]);
+                q0[u] = a.q[n];
+                q1[u] = a.q[N + n];
+                if (D == 3) q2[u] = a.q[2 * N + n];
+                tot[u] = a.ctot[n];
+                // the lattice kernel of this step was the last reader of the
+                // owner count: clear it for the next footprint
+                a.nown[n] = 0;
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < UN; u++) {
+            if (v[u] == 0u) continue;
+            const int cnt = (int)(v[u] & LIST_COUNT_MASK);
+            const double sh = (double)cnt / (double)tot[u];
+            const double t0 = sh * q0[u], t1 = sh * q1[u];
+            const double rx = ndisp(a.g, 0, ix[u], xp0);
+            const double ry = ndisp(a.g, 1, iy[u], xp1);
+            acc_add(F[0], t0);
+            acc_add(F[1], t1);
+            if (D == 3) {
+                const double t2 = sh * q2[u];
+                const double rz = ndisp(a.g, 2, iz[u], xp2);
+                acc_add(F[2], t2);
+                acc_add(T[0], ry * t2 - rz * t1);
+                acc_add(T[1], rz * t0 - rx * t2);
+                acc_add(T[2], rx * t1 - ry * t0);
+            } else {
+                acc_add(T[2], rx * t1 - ry * t0);
+            }
         }
     }
 #pragma unroll
@@ -341,6 +343,26 @@ __global__ __launch_bounds__(256) void k_force(ForceArgs a) {
             a.P.Fh[d * P + p] = fv;
             a.P.Th[d * P + p] = tv;
         }
+    }
+}
+
+// q_n of the last step at the nodes of the current footprint lists (the nodes
+// the lattice kernel covered); `out` [D][N] is zero elsewhere beforehand.
+template <int D>
+__global__ void k_list_q(ForceArgs a, double *out) {
+    const int p = blockIdx.x;
+    const int P = a.P.np;
+    const int len = a.P.list_len[p];
+    const int lo0 = a.P.bb[p], lo1 = a.P.bb[P + p], lo2 = a.P.bb[2 * P + p];
+    const uint32_t *list = a.P.list + (int64_t)p * a.P.list_cap;
+    const int64_t N = a.g.N;
+    for (int e = threadIdx.x; e < len; e += blockDim.x) {
+        const uint32_t v = list[e];
+        const int ix = wrap1(a.g, 0, lo0 + (int)((v >> 10) & 127u));
+        const int iy = wrap1(a.g, 1, lo1 + (int)((v >> 17) & 127u));
+        const int iz = D == 3 ? wrap1(a.g, 2, lo2 + (int)((v >> 24) & 127u)) : 0;
+        const int64_t n = (int64_t)ix + (int64_t)a.g.nx * ((int64_t)iy + (int64_t)a.g.ny * iz);
+        for (int d = 0; d < D; d++) out[d * N + n] = a.q[d * N + n];
     }
 }
 
@@ -519,13 +541,6 @@ __global__ void k_integrate(CellArgs a) {
 // ---------------------------------------------------------------- launchers
 static unsigned blocks_for(int n, int per) { return (unsigned)((n + per - 1) / per); }
 
-hipError_t launch_foot_clear(const FootArgs &a, int D, hipStream_t s) {
-    if (a.P.np == 0) return hipSuccess;
-    if (D == 2) hipLaunchKernelGGL(k_foot_clear, dim3((unsigned)a.P.np), dim3(64), 0, s, a, D);
-    else hipLaunchKernelGGL(k_foot_clear, dim3((unsigned)a.P.np), dim3(128), 0, s, a, D);
-    return hipGetLastError();
-}
-
 template <int D>
 static hipError_t paint_s(const FootArgs &a, hipStream_t s, int block) {
     const dim3 g((unsigned)a.P.np), b((unsigned)block);
@@ -544,13 +559,21 @@ static hipError_t paint_s(const FootArgs &a, hipStream_t s, int block) {
 
 hipError_t launch_foot_paint(const FootArgs &a, int D, hipStream_t s) {
     if (a.P.np == 0) return hipSuccess;
-    return D == 2 ? paint_s<2>(a, s, 128) : paint_s<3>(a, s, 128);
+    return D == 2 ? paint_s<2>(a, s, 128) : paint_s<3>(a, s, 256);
 }
 
 hipError_t launch_force(const ForceArgs &a, hipStream_t s) {
     if (a.P.np == 0) return hipSuccess;
     if (a.D == 2) hipLaunchKernelGGL(k_force<2>, dim3((unsigned)a.P.np), dim3(64), 0, s, a);
     else hipLaunchKernelGGL(k_force<3>, dim3((unsigned)a.P.np), dim3(128), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_list_q(const ForceArgs &a, double *out, hipStream_t s) {
+    hipError_t e = launch_fill_u64((uint64_t *)out, 0ull, (int64_t)a.D * a.g.N, s);
+    if (e != hipSuccess || a.P.np == 0) return e;
+    if (a.D == 2) hipLaunchKernelGGL(k_list_q<2>, dim3((unsigned)a.P.np), dim3(128), 0, s, a, out);
+    else hipLaunchKernelGGL(k_list_q<3>, dim3((unsigned)a.P.np), dim3(256), 0, s, a, out);
     return hipGetLastError();
 }
 

@@ -263,7 +263,6 @@ hipError_t enqueue_step(lbm_ctx *c, int from, hipStream_t s) {
     if (c->np > 0) {
         FootArgs fa = foot_args(c);
         phase_begin(c, 0, s);
-        if ((e = launch_foot_clear(fa, c->L.D, s)) != hipSuccess) return e;
         if ((e = launch_foot_paint(fa, c->L.D, s)) != hipSuccess) return e;
         phase_end(c, s);
     }
@@ -276,6 +275,7 @@ hipError_t enqueue_step(lbm_ctx *c, int from, hipStream_t s) {
         fo.g = c->g;
         fo.ctot = wsp<int>(c, c->L.off_ctot);
         fo.q = wsp<double>(c, c->L.off_q);
+        fo.nown = wsp<uint8_t>(c, c->L.off_nown);
         fo.D = c->L.D;
         phase_begin(c, 2, s);
         if ((e = launch_force(fo, s)) != hipSuccess) return e;
@@ -350,12 +350,6 @@ int produce_to(lbm_ctx *c, void *out, size_t bytes, int kind, F produce) {
     return LBM_OK;
 }
 
-__global__ void k_masked_q(Geom g, int D, const uint8_t *nown, const double *q, double *out) {
-    const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (n >= g.N) return;
-    const bool cov = nown[n] != 0;
-    for (int d = 0; d < D; d++) out[(int64_t)d * g.N + n] = cov ? q[(int64_t)d * g.N + n] : 0.0;
-}
 
 }  // namespace
 
@@ -681,10 +675,14 @@ int lbm_get_q(lbm_ctx *c, double *q, int ptr_kind) {
     if (!c) return LBM_E_INVALID;
     const size_t bytes = (size_t)c->L.D * c->L.N * 8;
     return produce_to(c, q, bytes, ptr_kind, [&](void *dst) {
-        const int64_t blocks = (c->L.N + 255) / 256;
-        hipLaunchKernelGGL(k_masked_q, dim3((unsigned)blocks), dim3(256), 0, c->stream, c->g, c->L.D,
-                           wsp<uint8_t>(c, c->L.off_nown), wsp<double>(c, c->L.off_q), (double *)dst);
-        return hipGetLastError();
+        ForceArgs fo;
+        fo.P = particles(c);
+        fo.g = c->g;
+        fo.ctot = wsp<int>(c, c->L.off_ctot);
+        fo.q = wsp<double>(c, c->L.off_q);
+        fo.nown = wsp<uint8_t>(c, c->L.off_nown);
+        fo.D = c->L.D;
+        return launch_list_q(fo, (double *)dst, c->stream);
     });
 }
 

@@ -125,3 +125,17 @@ def test_autotune_resets_and_keeps_results(gpu_lib):
     ref.run(8)
     for k in range(len(boxes)):
         assert np.array_equal(b.get_f(k), ref.get_f(k))
+
+
+def test_initial_velocity_is_kept_without_forcing(gpu_lib):
+    """A box without spheres or body force started at a uniform velocity
+    keeps it (to binary32 rounding); a box without init_velocity starts at
+    rest and stays there bit for bit."""
+    u0 = (0.03, -0.01, 0.02)
+    b = gpu_lib.Batch([{"edge": 32, "tau": 0.8, "init_velocity": u0},
+                       {"edge": 32, "tau": 0.8}], samples=4)
+    b.run(50)
+    U = b.mean_velocity()
+    say("uniform box after 50 steps:", U[0])
+    assert np.allclose(U[0], u0, rtol=1e-5, atol=1e-9)
+    assert np.array_equal(U[1], np.zeros(3))

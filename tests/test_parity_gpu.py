@@ -221,6 +221,18 @@ def test_slot_overflow_is_reported(gpu_lib):
     assert ei.value.code == -5
 
 
+def test_runaway_particle_is_reported(gpu_lib):
+    """A particle that moves more than a box length in one step leaves the
+    box after the single periodic wrap of the integrator: the next footprint
+    gives it no nodes and the step reports LBM_E_NONFINITE."""
+    say("runaway particle")
+    s = gpu_lib.Simulation(3, (24, 24, 24), 0.8, samples=2, kn=0.0, max_particles=1)
+    s.set_particles([[12.0, 12.0, 12.0]], vel=[[60.0, 0.0, 0.0]], radius=[3.0], rho_s=[1000.0])
+    with pytest.raises(gpu_lib.LbmError) as ei:
+        s.step(2)
+    assert ei.value.code == -4
+
+
 def test_invalid_inputs_rejected(gpu_lib):
     say("invalid inputs")
     with pytest.raises(gpu_lib.LbmError):
