@@ -25,11 +25,16 @@ namespace lbimb {
 
 __device__ __forceinline__ int wrapL(int c, int L) { return c < 0 ? c + L : (c >= L ? c - L : c); }
 
+// Element (i, x, row) of a box's state, row = y + L z: the 19 direction rows
+// of one lattice row are contiguous (the single-box layout f[z][y][i][x]).
+__device__ __forceinline__ uint32_t belem(int Lb, int i, int x, int row) {
+    return ((uint32_t)row * 19u + (uint32_t)i) * (uint32_t)Lb + (uint32_t)x;
+}
+
 // One tile of one box for one step.
 __device__ __forceinline__ void batch_tile(const BatchArgs &a, const BatchBox &bx, int tile, int parity) {
     using L = D3Q19;
     const int Lb = bx.L;
-    const uint64_t N = (uint64_t)Lb * Lb * Lb;
     const float *A = (parity ? a.B : a.A) + bx.off;
     float *B = (parity ? a.A : a.B) + bx.off;
     const int nodes = Lb * bx.rows;
@@ -52,15 +57,14 @@ __device__ __forceinline__ void batch_tile(const BatchArgs &a, const BatchBox &b
             const int sx = L::cx[i] == 0 ? x : (L::cx[i] > 0 ? xm : xp);
             const int sy = L::cy[i] == 0 ? y : (L::cy[i] > 0 ? ym : yp);
             const int sz = L::cz[i] == 0 ? z : (L::cz[i] > 0 ? zm : zp);
-            const uint32_t src = (uint32_t)sx + (uint32_t)Lb * ((uint32_t)sy + (uint32_t)Lb * (uint32_t)sz);
-            gg[i] = A[(uint64_t)i * N + src];
+            gg[i] = A[belem(Lb, i, sx, sy + Lb * sz)];
         }
         const int cnt = a.cnt[bx.noff + n];
         const bool wave_fluid = !__any(cnt != 0);
         const int cc = cnt < a.Smax ? cnt : a.Smax;
         const float beta = cnt != 0 ? beta_t[cc] : 0.0f;
         const float ar = cnt != 0 ? arel_t[cc] : bx.arel0f;
-        auto put = [&](int i, float v) { __builtin_nontemporal_store(v, &B[(uint64_t)i * N + n]); };
+        auto put = [&](int i, float v) { __builtin_nontemporal_store(v, &B[belem(Lb, i, x, row)]); };
         float mom[3];
         shifted_node<L, false>(gg, wave_fluid, beta, ar, 0.0f, 0.0f, 0.0f, bx.cgf, put, mom);
         if (cnt != 0) {
@@ -198,9 +202,10 @@ __global__ __launch_bounds__(256) void k_batch_mean(BatchArgs a, int parity, dou
     for (uint64_t n = threadIdx.x; n < N; n += blockDim.x) {
         // moments of the post-collision populations: the same total as the
         // streamed ones on a periodic box
+        const int x = (int)(n % (uint64_t)bx.L), row = (int)(n / (uint64_t)bx.L);
 #pragma unroll
         for (int i = 1; i < L::Q; i++) {
-            const double g = (double)A[(uint64_t)i * N + n];
+            const double g = (double)A[belem(bx.L, i, x, row)];
             if (L::cx[i]) s[0] += L::cx[i] * g;
             if (L::cy[i]) s[1] += L::cy[i] * g;
             if (L::cz[i]) s[2] += L::cz[i] * g;
@@ -229,7 +234,7 @@ __global__ void k_batch_get_f(BatchArgs a, int b, int parity, double *f) {
 #pragma unroll
     for (int i = 0; i < L::Q; i++) {
         const int sx = wrapL(x - L::cx[i], Lb), sy = wrapL(y - L::cy[i], Lb), sz = wrapL(z - L::cz[i], Lb);
-        const float g = A[(uint64_t)i * N + (uint64_t)sx + (uint64_t)Lb * ((uint64_t)sy + (uint64_t)Lb * sz)];
+        const float g = A[belem(Lb, i, sx, sy + Lb * sz)];
         f[(uint64_t)i * N + n] = L::w[L::wc[i]] + (double)g;
     }
 }
@@ -246,10 +251,11 @@ __global__ void k_batch_init(BatchArgs a) {
     const uint64_t N = (uint64_t)bx.L * bx.L * bx.L;
     const uint64_t n = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (n >= N) return;
+    const int x = (int)(n % (uint64_t)bx.L), row = (int)(n / (uint64_t)bx.L);
 #pragma unroll
     for (int i = 0; i < 19; i++) {
-        a.A[bx.off + (uint64_t)i * N + n] = bx.g0[i];
-        a.B[bx.off + (uint64_t)i * N + n] = bx.g0[i];
+        a.A[bx.off + belem(bx.L, i, x, row)] = bx.g0[i];
+        a.B[bx.off + belem(bx.L, i, x, row)] = bx.g0[i];
     }
 }
 

@@ -69,15 +69,24 @@ struct Geom {
 };
 
 // Arguments of the fused stream-collide-IMB kernel.
+// Per-node IMB exchange record, written by the lattice kernel at covered
+// nodes and read by the force kernel: q_n = beta sum_i Omega_i c_i (binary64,
+// z component 0 in 2D) and the total sub-sample count.  32 bytes, so one
+// record is one aligned pair of 16-byte stores / loads.
+struct alignas(32) QRec {
+    double q[3];
+    int tot;
+    int pad;
+};
+
 struct LBArgs {
     const void *A;         // post-collision populations of the previous step
     void *B;               // post-collision populations of this step
-    const uint8_t *nown;   // owners per node
+    uint8_t *nown;         // owners per node; zeroed here once read (last reader in the step)
     const uint32_t *slots; // [MAX_OWNERS][N] (pid << 10 | count)
     const double *beta_tab;   // beta(eps) for count 0..Smax
     const double *arel_tab;   // (1 - beta) / tau for count 0..Smax
-    double *q;             // [D][N] IMB momentum exchange
-    int *ctot;             // [N] total sub-sample count at covered nodes
+    QRec *qr;              // [N] IMB exchange records (covered nodes)
     const double *px, *pv, *pw;  // particle SoA
     int np;
     Geom g;
@@ -102,9 +111,7 @@ struct FootArgs {
 struct ForceArgs {
     Particles P;
     Geom g;
-    const int *ctot;
-    const double *q;
-    uint8_t *nown;  // owner counts, zeroed at the listed nodes once read
+    const QRec *qr;
     int D;
 };
 
@@ -167,6 +174,7 @@ int batch_persistent_grid();
 
 // launchers (lb_kernels.hip)
 hipError_t launch_lb(int lattice, int storage, const LBArgs &a, hipStream_t s);
+hipError_t launch_fill_rest_f64(int lattice, const Geom &g, double *A, hipStream_t s);
 hipError_t launch_get_f(int lattice, int storage, const Geom &g, const void *A, double *f,
                         hipStream_t s);
 hipError_t launch_set_f(int lattice, int storage, const Geom &g, const double *f, void *A,

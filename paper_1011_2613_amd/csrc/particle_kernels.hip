@@ -100,6 +100,16 @@ __device__ __forceinline__ int wrap1(const Geom &g, int axis, int c) {
 
 constexpr uint32_t LIST_COUNT_MASK = 1023u;
 
+// floor(v / d) for 0 <= v < 2^24 and 1 <= d < 2^12: binary32 estimate from the
+// reciprocal, then one exact integer correction step.
+__device__ __forceinline__ int div_small(int v, int d, float inv_d) {
+    int q = (int)((float)v * inv_d);
+    const int r = v - q * d;
+    if (r < 0) q -= 1;
+    else if (r >= d) q += 1;
+    return q;
+}
+
 __device__ __forceinline__ uint32_t list_entry(int count, int kx, int ky, int kz) {
     return (uint32_t)count | ((uint32_t)kx << 10) | ((uint32_t)ky << 17) | ((uint32_t)kz << 24);
 }
@@ -127,13 +137,42 @@ __device__ __forceinline__ int block_scan(int v, int &total) {
     return before + x - v;
 }
 
-// Footprint of one particle, one workgroup, one bounding-box node per thread
-// and pass: the thread computes the node's sample count once, a workgroup
-// prefix sum over "covered" gives its place in the particle's list (node
-// order x fastest, so the list is the same on every run), and the thread
-// claims an owner slot and writes its list entry.
+// Conservative classification of a node from per-axis distance bounds: 0 when
+// every sub-cell sample is certainly outside, S^D when every sample is
+// certainly inside, -1 otherwise.  With h = 1/2 - 1/(2S) the largest sample
+// offset, the sum of squares of every sample lies in [lo, hi] built from
+// max(|d| - h, 0) and |d| + h; rounding moves the tested sums and the bounds
+// by a few units in the last place, far inside the 1e-14 relative margins,
+// so a decided node gets exactly the count the per-sample test gives.
+template <int D, int S>
+__device__ __forceinline__ int classify(double d0, double d1, double d2, double R2) {
+    const double h = 0.5 - 0.5 / (double)S;
+    const double a0 = fabs(d0), a1 = fabs(d1), a2 = fabs(d2);
+    const double m0 = fmax(a0 - h, 0.0), m1 = fmax(a1 - h, 0.0), m2 = fmax(a2 - h, 0.0);
+    const double M0 = a0 + h, M1 = a1 + h, M2 = a2 + h;
+    double lo = m0 * m0 + m1 * m1, hi = M0 * M0 + M1 * M1;
+    if (D == 3) {
+        lo = lo + m2 * m2;
+        hi = hi + M2 * M2;
+    }
+    if (lo * (1.0 - 1e-14) > R2) return 0;
+    if (hi * (1.0 + 1e-14) <= R2) return D == 3 ? S * S * S : S * S;
+    return -1;
+}
+
+// Footprint of one particle, one workgroup.  The bounding box is taken in
+// chunks of nodes: (A) every node is classified by distance bounds, undecided
+// nodes are queued in LDS; (B) the queued nodes get the exact per-sample count,
+// the workgroup's lanes all busy with such nodes; (C) in node order (x
+// fastest), a workgroup prefix sum over covered nodes gives each its place in
+// the particle's list, and the thread claims an owner slot and writes the
+// entry, so the list is the same on every run.
 template <int D, int S>
 __global__ __launch_bounds__(256) void k_foot_paint(FootArgs a) {
+    constexpr int CHUNK = 1024;
+    __shared__ uint16_t s_cnt[CHUNK];
+    __shared__ uint16_t s_todo[CHUNK];
+    __shared__ int s_ntodo;
     const int p = blockIdx.x;
     const int P = a.P.np;
     int lo[3], hi[3];
@@ -163,39 +202,67 @@ __global__ __launch_bounds__(256) void k_foot_paint(FootArgs a) {
     const int64_t N = a.g.N;
     const int cap = a.P.list_cap;
     uint32_t *list = a.P.list + (int64_t)p * cap;
+    const float inv0 = 1.0f / (float)ext0, inv1 = 1.0f / (float)ext1;
+    // node of a bounding-box item: lattice coordinates (iy < 0 beyond a wall)
+    auto node_of = [&](int item, int &kx, int &ky, int &kz, int &ix, int &iy, int &iz) {
+        const int rest = div_small(item, ext0, inv0);
+        kx = item - rest * ext0;
+        kz = div_small(rest, ext1, inv1);
+        ky = rest - kz * ext1;
+        iy = wrap1(a.g, 1, lo[1] + ky);
+        ix = wrap1(a.g, 0, lo[0] + kx);
+        iz = D == 3 ? wrap1(a.g, 2, lo[2] + kz) : 0;
+    };
     int base = 0;
-    for (int it0 = 0; it0 < items; it0 += blockDim.x) {
-        const int item = it0 + threadIdx.x;
-        int count = 0, kx = 0, ky = 0, kz = 0;
-        int64_t n = 0;
-        if (item < items) {
-            kx = item % ext0;
-            const int rest = item / ext0;
-            ky = rest % ext1;
-            kz = rest / ext1;
-            const int iy = wrap1(a.g, 1, lo[1] + ky);
-            if (iy >= 0) {
-                const int ix = wrap1(a.g, 0, lo[0] + kx);
-                const int iz = D == 3 ? wrap1(a.g, 2, lo[2] + kz) : 0;
-                count = sample_count<D, S>(ndisp(a.g, 0, ix, xp0), ndisp(a.g, 1, iy, xp1),
-                                           D == 3 ? ndisp(a.g, 2, iz, xp2) : 0.0, R2);
-                n = (int64_t)ix + (int64_t)a.g.nx * ((int64_t)iy + (int64_t)a.g.ny * iz);
+    for (int c0 = 0; c0 < items; c0 += CHUNK) {
+        const int nc = items - c0 < CHUNK ? items - c0 : CHUNK;
+        if (threadIdx.x == 0) s_ntodo = 0;
+        __syncthreads();
+        // (A) classify
+        for (int i = threadIdx.x; i < nc; i += blockDim.x) {
+            int kx, ky, kz, ix, iy, iz;
+            node_of(c0 + i, kx, ky, kz, ix, iy, iz);
+            int cls = 0;
+            if (iy >= 0)
+                cls = classify<D, S>(ndisp(a.g, 0, ix, xp0), ndisp(a.g, 1, iy, xp1),
+                                     D == 3 ? ndisp(a.g, 2, iz, xp2) : 0.0, R2);
+            if (cls < 0) s_todo[atomicAdd(&s_ntodo, 1)] = (uint16_t)i;
+            else s_cnt[i] = (uint16_t)cls;
+        }
+        __syncthreads();
+        // (B) exact per-sample counts of the undecided nodes
+        const int ntodo = s_ntodo;
+        for (int j = threadIdx.x; j < ntodo; j += blockDim.x) {
+            const int i = s_todo[j];
+            int kx, ky, kz, ix, iy, iz;
+            node_of(c0 + i, kx, ky, kz, ix, iy, iz);
+            s_cnt[i] = (uint16_t)sample_count<D, S>(ndisp(a.g, 0, ix, xp0), ndisp(a.g, 1, iy, xp1),
+                                                    D == 3 ? ndisp(a.g, 2, iz, xp2) : 0.0, R2);
+        }
+        __syncthreads();
+        // (C) list positions in node order, owner slots, list entries
+        for (int i0 = 0; i0 < nc; i0 += blockDim.x) {
+            const int i = i0 + threadIdx.x;
+            const int count = i < nc ? (int)s_cnt[i] : 0;
+            int total;
+            const int pos = base + block_scan(count > 0 ? 1 : 0, total);
+            if (count > 0) {
+                int kx, ky, kz, ix, iy, iz;
+                node_of(c0 + i, kx, ky, kz, ix, iy, iz);
+                const int64_t n = (int64_t)ix + (int64_t)a.g.nx * ((int64_t)iy + (int64_t)a.g.ny * iz);
+                uint32_t *word = (uint32_t *)(a.nown + (n & ~(int64_t)3));
+                const int sh = 8 * (int)(n & 3);
+                const uint32_t old = atomicAdd(word, 1u << sh);
+                const int slot = (int)((old >> sh) & 0xffu);
+                if (slot < MAX_OWNERS)
+                    a.slots[(int64_t)slot * N + n] = ((uint32_t)p << SLOT_COUNT_BITS) | (uint32_t)count;
+                else
+                    atomicOr(a.flags, FLAG_SLOT_OVERFLOW);
+                if (pos < cap) list[pos] = list_entry(count, kx, ky, kz);
             }
+            base += total;
         }
-        int total;
-        const int pos = base + block_scan(count > 0 ? 1 : 0, total);
-        if (count > 0) {
-            uint32_t *word = (uint32_t *)(a.nown + (n & ~(int64_t)3));
-            const int sh = 8 * (int)(n & 3);
-            const uint32_t old = atomicAdd(word, 1u << sh);
-            const int slot = (int)((old >> sh) & 0xffu);
-            if (slot < MAX_OWNERS)
-                a.slots[(int64_t)slot * N + n] = ((uint32_t)p << SLOT_COUNT_BITS) | (uint32_t)count;
-            else
-                atomicOr(a.flags, FLAG_SLOT_OVERFLOW);
-            if (pos < cap) list[pos] = list_entry(count, kx, ky, kz);
-        }
-        base += total;
+        __syncthreads();
     }
     if (threadIdx.x == 0) {
         if (base > cap) atomicOr(a.flags, FLAG_SLOT_OVERFLOW);
@@ -230,8 +297,7 @@ __device__ __forceinline__ double shfl_xor_d(double v, int m) {
 
 // One workgroup per particle over its footprint list: each entry gives the
 // node and the particle's sample count there; q_n and the node's total count
-// come from the lattice kernel.  The kernel also zeroes the owner count of
-// every listed node (the footprint of the next step starts from zero counts).  s_pn q_n and r_pn x (s_pn q_n) go into TwoSum
+// come from the lattice kernel.  s_pn q_n and r_pn x (s_pn q_n) go into TwoSum
 // accumulators; each wavefront merges its lanes with butterfly shuffles and
 // the first thread merges the wavefronts in a fixed order.
 // F_p = -sum, T_p = -sum.
@@ -247,7 +313,6 @@ __global__ __launch_bounds__(256) void k_force(ForceArgs a) {
     const int lo0 = a.P.bb[p], lo1 = a.P.bb[P + p], lo2 = a.P.bb[2 * P + p];
     const uint32_t *list = a.P.list + (int64_t)p * a.P.list_cap;
     const double xp0 = a.P.x[p], xp1 = a.P.x[P + p], xp2 = D == 3 ? a.P.x[2 * P + p] : 0.0;
-    const int64_t N = a.g.N;
     Acc F[3] = {{0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}};
     Acc T[3] = {{0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}};
     // UN entries per thread per round: all list and q loads of a round are
@@ -272,13 +337,11 @@ __global__ __launch_bounds__(256) void k_force(ForceArgs a) {
             tot[u] = 1;
             if (v[u] != 0u) {
                 const int64_t n = (int64_t)ix[u] + (int64_t)a.g.nx * ((int64_t)iy[u] + (int64_t)a.g.ny * iz[u]);
-                q0[u] = a.q[n];
-                q1[u] = a.q[N + n];
-                if (D == 3) q2[u] = a.q[2 * N + n];
-                tot[u] = a.ctot[n];
-                // the lattice kernel of this step was the last reader of the
-                // owner count: clear it for the next footprint
-                a.nown[n] = 0;
+                const QRec r = a.qr[n];
+                q0[u] = r.q[0];
+                q1[u] = r.q[1];
+                q2[u] = r.q[2];
+                tot[u] = r.tot;
             }
         }
 #pragma unroll
@@ -362,7 +425,7 @@ __global__ void k_list_q(ForceArgs a, double *out) {
         const int iy = wrap1(a.g, 1, lo1 + (int)((v >> 17) & 127u));
         const int iz = D == 3 ? wrap1(a.g, 2, lo2 + (int)((v >> 24) & 127u)) : 0;
         const int64_t n = (int64_t)ix + (int64_t)a.g.nx * ((int64_t)iy + (int64_t)a.g.ny * iz);
-        for (int d = 0; d < D; d++) out[d * N + n] = a.q[d * N + n];
+        for (int d = 0; d < D; d++) out[d * N + n] = a.qr[n].q[d];
     }
 }
 

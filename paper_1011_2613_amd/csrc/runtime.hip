@@ -34,7 +34,7 @@ struct Layout {
     int64_t N;
     int P;
     int64_t cell_budget;
-    size_t off_fA, off_fB, off_nown, off_slots, off_q, off_ctot, off_beta, off_arel;
+    size_t off_fA, off_fB, off_nown, off_slots, off_qr, off_beta, off_arel;
     size_t off_x, off_v, off_w, off_R, off_m, off_I, off_fixed, off_Fh, off_Th, off_Fc, off_bb;
     size_t off_list, off_list_len;
     int list_cap;
@@ -78,8 +78,7 @@ Layout make_layout(const lbm_config *c) {
     L.off_fB = take(fs);
     L.off_nown = take(((size_t)L.N + 3) / 4 * 4);
     L.off_slots = take((size_t)MAX_OWNERS * L.N * 4);
-    L.off_q = take((size_t)L.D * L.N * 8);
-    L.off_ctot = take((size_t)L.N * 4);
+    L.off_qr = take((size_t)L.N * sizeof(QRec));
     L.off_beta = take((size_t)(L.Smax + 1) * 8);
     L.off_arel = take((size_t)(L.Smax + 1) * 8);
     const size_t P = (size_t)L.P;
@@ -120,6 +119,11 @@ struct lbm_ctx {
     char *ws;
     hipStream_t stream;
     hipStream_t cap_stream;
+    // the DEM cell list and contact forces run on a side stream beside the
+    // footprint, lattice and force kernels (they only read positions and
+    // velocities, which change in the integration at the end of the step)
+    hipStream_t side_stream;
+    hipEvent_t ev_fork[2], ev_join[2];
     int cur;  // 0: state in fA, 1: state in fB
     int64_t t;
     int np;
@@ -218,8 +222,7 @@ LBArgs lb_args(lbm_ctx *c, int from) {
     a.slots = wsp<uint32_t>(c, c->L.off_slots);
     a.beta_tab = wsp<double>(c, c->L.off_beta);
     a.arel_tab = wsp<double>(c, c->L.off_arel);
-    a.q = wsp<double>(c, c->L.off_q);
-    a.ctot = wsp<int>(c, c->L.off_ctot);
+    a.qr = wsp<QRec>(c, c->L.off_qr);
     a.px = wsp<double>(c, c->L.off_x);
     a.pv = wsp<double>(c, c->L.off_v);
     a.pw = wsp<double>(c, c->L.off_w);
@@ -256,11 +259,23 @@ void phase_end(lbm_ctx *c, hipStream_t s) {
     c->ev_used++;
 }
 
-// Queue one complete time step reading state `from`.
-hipError_t enqueue_step(lbm_ctx *c, int from, hipStream_t s) {
+// Queue one complete time step reading state `from`.  `slot` selects the
+// fork/join event pair (two steps are captured per graph).
+hipError_t enqueue_step(lbm_ctx *c, int from, hipStream_t s, int slot) {
     hipError_t e;
     const int lattice = c->cfg.lattice, storage = c->cfg.storage;
     if (c->np > 0) {
+        CellArgs ca = cell_args(c);
+        hipStream_t d = c->side_stream;
+        if ((e = hipEventRecord(c->ev_fork[slot], s)) != hipSuccess) return e;
+        if ((e = hipStreamWaitEvent(d, c->ev_fork[slot], 0)) != hipSuccess) return e;
+        phase_begin(c, 3, d);
+        if ((e = launch_cells(ca, d)) != hipSuccess) return e;
+        phase_end(c, d);
+        phase_begin(c, 4, d);
+        if ((e = launch_dem(ca, d)) != hipSuccess) return e;
+        phase_end(c, d);
+        if ((e = hipEventRecord(c->ev_join[slot], d)) != hipSuccess) return e;
         FootArgs fa = foot_args(c);
         phase_begin(c, 0, s);
         if ((e = launch_foot_paint(fa, c->L.D, s)) != hipSuccess) return e;
@@ -273,20 +288,13 @@ hipError_t enqueue_step(lbm_ctx *c, int from, hipStream_t s) {
         ForceArgs fo;
         fo.P = particles(c);
         fo.g = c->g;
-        fo.ctot = wsp<int>(c, c->L.off_ctot);
-        fo.q = wsp<double>(c, c->L.off_q);
-        fo.nown = wsp<uint8_t>(c, c->L.off_nown);
+        fo.qr = wsp<QRec>(c, c->L.off_qr);
         fo.D = c->L.D;
         phase_begin(c, 2, s);
         if ((e = launch_force(fo, s)) != hipSuccess) return e;
         phase_end(c, s);
+        if ((e = hipStreamWaitEvent(s, c->ev_join[slot], 0)) != hipSuccess) return e;
         CellArgs ca = cell_args(c);
-        phase_begin(c, 3, s);
-        if ((e = launch_cells(ca, s)) != hipSuccess) return e;
-        phase_end(c, s);
-        phase_begin(c, 4, s);
-        if ((e = launch_dem(ca, s)) != hipSuccess) return e;
-        phase_end(c, s);
         phase_begin(c, 5, s);
         if ((e = launch_integrate(ca, s)) != hipSuccess) return e;
         phase_end(c, s);
@@ -304,8 +312,8 @@ void drop_graphs(lbm_ctx *c) {
 int build_graph(lbm_ctx *c, int from) {
     hipGraph_t graph;
     HIPCHK(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
-    hipError_t e1 = enqueue_step(c, from, c->cap_stream);
-    hipError_t e2 = e1 == hipSuccess ? enqueue_step(c, 1 - from, c->cap_stream) : e1;
+    hipError_t e1 = enqueue_step(c, from, c->cap_stream, 0);
+    hipError_t e2 = e1 == hipSuccess ? enqueue_step(c, 1 - from, c->cap_stream, 1) : e1;
     hipError_t e3 = hipStreamEndCapture(c->cap_stream, &graph);
     if (e2 != hipSuccess) return fail(c, LBM_E_HIP, "graph capture: %s", hipGetErrorString(e2));
     if (e3 != hipSuccess) return fail(c, LBM_E_HIP, "graph capture end: %s", hipGetErrorString(e3));
@@ -431,6 +439,24 @@ int lbm_create(const lbm_config *cfg, void *workspace, size_t ws_bytes, void *hi
         delete c;
         return fail(nullptr, LBM_E_HIP, "hipStreamCreateWithFlags failed");
     }
+    if (hipStreamCreateWithFlags(&c->side_stream, hipStreamNonBlocking) != hipSuccess) {
+        (void)hipStreamDestroy(c->cap_stream);
+        delete c;
+        return fail(nullptr, LBM_E_HIP, "hipStreamCreateWithFlags failed");
+    }
+    {
+        bool ok = true;
+        for (int k = 0; k < 2; k++) {
+            ok = ok && hipEventCreateWithFlags(&c->ev_fork[k], hipEventDisableTiming) == hipSuccess;
+            ok = ok && hipEventCreateWithFlags(&c->ev_join[k], hipEventDisableTiming) == hipSuccess;
+        }
+        if (!ok) {
+            (void)hipStreamDestroy(c->side_stream);
+            (void)hipStreamDestroy(c->cap_stream);
+            delete c;
+            return fail(nullptr, LBM_E_HIP, "hipEventCreateWithFlags failed");
+        }
+    }
     // beta(eps) (Eq. 2) and (1 - beta)/tau for every possible clamped count
     std::vector<double> beta(L.Smax + 1), arel(L.Smax + 1);
     const double tau = cfg->tau;
@@ -445,21 +471,13 @@ int lbm_create(const lbm_config *cfg, void *workspace, size_t ws_bytes, void *hi
     chk(hipMemcpyAsync(wsp<double>(c, L.off_arel), arel.data(), arel.size() * 8, hipMemcpyHostToDevice, c->stream));
     chk(launch_fill_u32(wsp<uint32_t>(c, L.off_nown), 0u, (int64_t)((L.N + 3) / 4), c->stream));
     chk(launch_fill_u32(wsp<uint32_t>(c, L.off_flags), 0u, 16, c->stream));
-    chk(launch_fill_u32(wsp<uint32_t>(c, L.off_q), 0u, (int64_t)L.D * L.N * 2, c->stream));
+    chk(launch_fill_u32(wsp<uint32_t>(c, L.off_qr), 0u, (int64_t)L.N * (int64_t)(sizeof(QRec) / 4), c->stream));
     // fluid at rest: f = f^eq(1, 0) = w_i  (shifted storage: g = 0)
     {
         const int Q = L.Q;
-        std::vector<double> wv(Q);
-        const double *w = cfg->lattice == LBM_D2Q9 ? D2Q9::w : D3Q19::w;
-        const int *wc = cfg->lattice == LBM_D2Q9 ? D2Q9::wc : D3Q19::wc;
-        for (int i = 0; i < Q; i++) wv[i] = w[wc[i]];
         if (cfg->storage == LBM_FP64) {
             // f^eq_i(1, 0) = w_i exactly (c.u = 0, u.u = 0)
-            for (int i = 0; i < Q; i++) {
-                uint64_t bits;
-                memcpy(&bits, &wv[i], 8);
-                chk(launch_fill_u64(wsp<uint64_t>(c, L.off_fA) + (size_t)i * L.N, bits, L.N, c->stream));
-            }
+            chk(launch_fill_rest_f64(cfg->lattice, c->g, wsp<double>(c, L.off_fA), c->stream));
         } else {
             const size_t bytes = (size_t)Q * L.N * store_bytes(cfg->storage);
             chk(launch_fill_u32(wsp<uint32_t>(c, L.off_fA), 0u, (int64_t)((bytes + 3) / 4), c->stream));
@@ -467,6 +485,11 @@ int lbm_create(const lbm_config *cfg, void *workspace, size_t ws_bytes, void *hi
     }
     chk(hipStreamSynchronize(c->stream));
     if (r != LBM_OK) {
+        for (int k = 0; k < 2; k++) {
+            (void)hipEventDestroy(c->ev_fork[k]);
+            (void)hipEventDestroy(c->ev_join[k]);
+        }
+        (void)hipStreamDestroy(c->side_stream);
         (void)hipStreamDestroy(c->cap_stream);
         delete c;
         return r;  // message already in the thread's last error
@@ -483,6 +506,12 @@ void lbm_destroy(lbm_ctx *c) {
         (void)hipEventDestroy(e.a);
         (void)hipEventDestroy(e.b);
     }
+    (void)hipStreamSynchronize(c->side_stream);
+    for (int k = 0; k < 2; k++) {
+        (void)hipEventDestroy(c->ev_fork[k]);
+        (void)hipEventDestroy(c->ev_join[k]);
+    }
+    (void)hipStreamDestroy(c->side_stream);
     (void)hipStreamDestroy(c->cap_stream);
     delete c;
 }
@@ -678,9 +707,7 @@ int lbm_get_q(lbm_ctx *c, double *q, int ptr_kind) {
         ForceArgs fo;
         fo.P = particles(c);
         fo.g = c->g;
-        fo.ctot = wsp<int>(c, c->L.off_ctot);
-        fo.q = wsp<double>(c, c->L.off_q);
-        fo.nown = wsp<uint8_t>(c, c->L.off_nown);
+        fo.qr = wsp<QRec>(c, c->L.off_qr);
         fo.D = c->L.D;
         return launch_list_q(fo, (double *)dst, c->stream);
     });
@@ -737,7 +764,7 @@ int lbm_step(lbm_ctx *c, int64_t nsteps) {
     hipError_t e;
     if (c->timing) {
         for (int64_t k = 0; k < nsteps; k++) {
-            if ((e = enqueue_step(c, c->cur, c->stream)) != hipSuccess)
+            if ((e = enqueue_step(c, c->cur, c->stream, 0)) != hipSuccess)
                 return fail(c, LBM_E_HIP, "step: %s", hipGetErrorString(e));
             c->cur ^= 1;
             c->t++;
@@ -758,7 +785,7 @@ int lbm_step(lbm_ctx *c, int64_t nsteps) {
         left -= 2 * pairs;
     }
     if (left == 1) {
-        if ((e = enqueue_step(c, c->cur, c->stream)) != hipSuccess)
+        if ((e = enqueue_step(c, c->cur, c->stream, 0)) != hipSuccess)
             return fail(c, LBM_E_HIP, "step: %s", hipGetErrorString(e));
         c->cur ^= 1;
         c->t++;
