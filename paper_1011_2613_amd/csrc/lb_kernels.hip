@@ -31,15 +31,16 @@
 
 namespace lbimb {
 
+// Periodic minimum image of a displacement, as selects (no branches, so the
+// loads that feed it can all be in flight together).
 __device__ __forceinline__ double disp_periodic(double d, double L) {
-    if (d > 0.5 * L) d = d - L;
-    else if (d < -0.5 * L) d = d + L;
-    return d;
+    const double dm = d - L, dp = d + L;
+    return d > 0.5 * L ? dm : (d < -0.5 * L ? dp : d);
 }
 
 // Displacement node coordinate - particle coordinate along axis a.
 __device__ __forceinline__ double node_disp(const Geom &g, int axis, int coord, double xp) {
-    double d = (double)coord - xp;
+    const double d = (double)coord - xp;
     if (axis == 0) return disp_periodic(d, g.Lx);
     if (axis == 1) return g.wall_y ? d : disp_periodic(d, g.Ly);
     return disp_periodic(d, g.Lz);
@@ -53,38 +54,49 @@ __device__ __forceinline__ void sort4(uint32_t &a, uint32_t &b, uint32_t &c, uin
 }
 
 // Solid velocity V_S at node (x,y,z): count-weighted mean of the owners'
-// rigid-body velocities v_p + omega_p x (x_n - x_p), owners in ascending id.
-// Returns the total sub-sample count.
+// rigid-body velocities v_p + omega_p x (x_n - x_p), owners in ascending id;
+// also the total sub-sample count and the node's beta and (1 - beta)/tau from
+// the tables.  Memory is read in three dependent rounds at most: the owner
+// records (all at once), the two table entries together with the first
+// owner's nine particle values, and one round per further owner.
 template <class L>
 __device__ __forceinline__ int solid_velocity(const LBArgs &a, int64_t n, int nown, int x, int y,
-                                              int z, double V[3]) {
+                                              int z, double V[3], double &beta, double &arel) {
     const int64_t N = a.g.N;
-    uint32_t r[4] = {0xffffffffu, 0xffffffffu, 0xffffffffu, 0xffffffffu};
     const int k = nown < MAX_OWNERS ? nown : MAX_OWNERS;
-    for (int j = 0; j < k; j++) r[j] = a.slots[(int64_t)j * N + n];
+    uint32_t r[4];
+#pragma unroll
+    for (int j = 0; j < MAX_OWNERS; j++) r[j] = j < k ? a.slots[(int64_t)j * N + n] : 0xffffffffu;
     sort4(r[0], r[1], r[2], r[3]);
     int total = 0;
+#pragma unroll
+    for (int j = 0; j < MAX_OWNERS; j++)
+        if (j < k) total += (int)(r[j] & ((1u << SLOT_COUNT_BITS) - 1u));
+    const int cc = total < a.Smax ? total : a.Smax;
+    beta = a.beta_tab[cc];
+    arel = a.arel_tab[cc];
     double num[3] = {0.0, 0.0, 0.0};
+    const int P = a.np;
 #pragma unroll
     for (int j = 0; j < MAX_OWNERS; j++) {
         if (j < k) {
             const int p = (int)(r[j] >> SLOT_COUNT_BITS);
             const int cnt = (int)(r[j] & ((1u << SLOT_COUNT_BITS) - 1u));
-            total += cnt;
-            const int P = a.np;
-            const double rx = node_disp(a.g, 0, x, a.px[p]);
-            const double ry = node_disp(a.g, 1, y, a.px[P + p]);
+            const double X0 = a.px[p], X1 = a.px[P + p], X2 = L::D == 3 ? a.px[2 * P + p] : 0.0;
+            const double U0 = a.pv[p], U1 = a.pv[P + p], U2 = L::D == 3 ? a.pv[2 * P + p] : 0.0;
+            const double W0 = L::D == 3 ? a.pw[p] : 0.0, W1 = L::D == 3 ? a.pw[P + p] : 0.0;
+            const double W2 = a.pw[2 * P + p];
+            const double rx = node_disp(a.g, 0, x, X0);
+            const double ry = node_disp(a.g, 1, y, X1);
             double vr[3];
             if (L::D == 3) {
-                const double rz = node_disp(a.g, 2, z, a.px[2 * P + p]);
-                const double wx = a.pw[p], wy = a.pw[P + p], wz = a.pw[2 * P + p];
-                vr[0] = a.pv[p] + (wy * rz - wz * ry);
-                vr[1] = a.pv[P + p] + (wz * rx - wx * rz);
-                vr[2] = a.pv[2 * P + p] + (wx * ry - wy * rx);
+                const double rz = node_disp(a.g, 2, z, X2);
+                vr[0] = U0 + (W1 * rz - W2 * ry);
+                vr[1] = U1 + (W2 * rx - W0 * rz);
+                vr[2] = U2 + (W0 * ry - W1 * rx);
             } else {
-                const double wz = a.pw[2 * P + p];
-                vr[0] = a.pv[p] - wz * ry;
-                vr[1] = a.pv[P + p] + wz * rx;
+                vr[0] = U0 - W2 * ry;
+                vr[1] = U1 + W2 * rx;
                 vr[2] = 0.0;
             }
             const double c = (double)cnt;
@@ -202,10 +214,8 @@ __device__ __forceinline__ void collide_f64(const LBArgs &a, uint64_t n, int x, 
     if (nown > MAX_OWNERS) atomicOr(a.flags, FLAG_SLOT_OVERFLOW);
     double V[3] = {0.0, 0.0, 0.0};
     int total = 0;
-    if (nown != 0) total = solid_velocity<L>(a, (int64_t)n, nown, x, y, z, V);
-    const int cc = total < a.Smax ? total : a.Smax;
-    const double beta = nown != 0 ? a.beta_tab[cc] : 0.0;
-    const double ar = nown != 0 ? a.arel_tab[cc] : a.arel0;
+    double beta = 0.0, ar = a.arel0;
+    if (nown != 0) total = solid_velocity<L>(a, (int64_t)n, nown, x, y, z, V, beta, ar);
     double VV = V[0] * V[0] + V[1] * V[1];
     if (L::D == 3) VV = VV + V[2] * V[2];
     Eq64<L> eqV = eq;
@@ -256,10 +266,10 @@ __device__ __forceinline__ void collide_shifted(const LBArgs &a, uint64_t n, int
     int total = 0;
     if (!wave_fluid && nown != 0) {
         if (nown > MAX_OWNERS) atomicOr(a.flags, FLAG_SLOT_OVERFLOW);
-        total = solid_velocity<L>(a, (int64_t)n, nown, x, y, z, Vd);
-        const int cc = total < a.Smax ? total : a.Smax;
-        beta = (float)a.beta_tab[cc];
-        ar = (float)a.arel_tab[cc];
+        double bd, ad;
+        total = solid_velocity<L>(a, (int64_t)n, nown, x, y, z, Vd, bd, ad);
+        beta = (float)bd;
+        ar = (float)ad;
     }
     float mom[3];
     shifted_node<L, ST == 2>(gg, wave_fluid, beta, ar, (float)Vd[0], (float)Vd[1], (float)Vd[2], a.cgf, put, mom);
@@ -282,9 +292,11 @@ __global__ __launch_bounds__(256) void k_lb(LBArgs a) {
     const int y = blockIdx.y, z = blockIdx.z;
     const uint64_t n = (uint64_t)x + (uint64_t)a.g.nx * ((uint64_t)y + (uint64_t)a.g.ny * (uint64_t)z);
     using T = typename Store<ST>::T;
+    // the owner count is read before the populations, so a wavefront with a
+    // covered node can start its owner-record reads while they arrive
+    const int nown = a.nown[n];
     T f[L::Q];
     gather<L, T>((const T *)a.A, a.g, x, y, z, f);
-    const int nown = a.nown[n];
     if (ST == 0) {
         double fd[L::Q];
 #pragma unroll

@@ -628,7 +628,7 @@ hipError_t launch_foot_paint(const FootArgs &a, int D, hipStream_t s) {
 hipError_t launch_force(const ForceArgs &a, hipStream_t s) {
     if (a.P.np == 0) return hipSuccess;
     if (a.D == 2) hipLaunchKernelGGL(k_force<2>, dim3((unsigned)a.P.np), dim3(64), 0, s, a);
-    else hipLaunchKernelGGL(k_force<3>, dim3((unsigned)a.P.np), dim3(128), 0, s, a);
+    else hipLaunchKernelGGL(k_force<3>, dim3((unsigned)a.P.np), dim3(64), 0, s, a);
     return hipGetLastError();
 }
 
