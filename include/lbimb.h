@@ -220,6 +220,13 @@ int lbm_batch_forces(lbm_batch *b, double *F, double *T, int ptr_kind);
  * [nbox][3] binary64. */
 int lbm_batch_mean_velocity(lbm_batch *b, double *U, int ptr_kind);
 
+/* Local flow seen by each sphere: the mean pre-collision fluid velocity
+ * (sum_i c_i f_i) / (sum_i f_i) over the nodes with no sub-cell sample of any
+ * sphere whose minimum-image distance to the sphere centre lies in [R + 1, 2R];
+ * [nspheres][3] binary64, spheres in box order.  Errors: LBM_E_INVALID,
+ * LBM_E_HIP. */
+int lbm_batch_shell_velocity(lbm_batch *b, double *u, int ptr_kind);
+
 /* Pre-collision populations f_i = w_i + g_i of one box, [19][L^3] binary64. */
 int lbm_batch_get_distributions(lbm_batch *b, int box, double *f, int ptr_kind);
 

@@ -49,7 +49,7 @@ _SYMBOLS = ("lbm_workspace_bytes", "lbm_create", "lbm_destroy", "lbm_set_particl
             "mlp_forward", "mlp_gradients", "mlp_train_step",
             "lbm_batch_workspace_bytes", "lbm_batch_create", "lbm_batch_destroy", "lbm_batch_set_tile_rows",
             "lbm_batch_run", "lbm_batch_set_active", "lbm_batch_forces", "lbm_batch_mean_velocity",
-            "lbm_batch_get_distributions", "lbm_batch_autotune", "lbm_batch_time")
+            "lbm_batch_get_distributions", "lbm_batch_autotune", "lbm_batch_time", "lbm_batch_shell_velocity")
 
 
 def load():
@@ -439,13 +439,14 @@ def _load_batch(L):
     L.lbm_batch_set_active.argtypes = [vp, vp]
     L.lbm_batch_forces.argtypes = [vp, vp, vp, C.c_int]
     L.lbm_batch_mean_velocity.argtypes = [vp, vp, C.c_int]
+    L.lbm_batch_shell_velocity.argtypes = [vp, vp, C.c_int]
     L.lbm_batch_get_distributions.argtypes = [vp, C.c_int, vp, C.c_int]
     L.lbm_batch_autotune.argtypes = [vp, C.c_int, vp, vp, vp, vp]
     L.lbm_batch_time.argtypes = [vp]
     L.lbm_batch_time.restype = i64
     for n in ("lbm_batch_workspace_bytes", "lbm_batch_create", "lbm_batch_set_tile_rows", "lbm_batch_run",
               "lbm_batch_set_active", "lbm_batch_forces", "lbm_batch_mean_velocity",
-              "lbm_batch_get_distributions", "lbm_batch_autotune"):
+              "lbm_batch_shell_velocity", "lbm_batch_get_distributions", "lbm_batch_autotune"):
         getattr(L, n).restype = C.c_int
     L._batch_ready = True
     return L
@@ -537,6 +538,13 @@ class Batch:
         U = np.zeros((self.nbox, 3))
         self._chk(load().lbm_batch_mean_velocity(self._ctx, _ptr(U), LBM_HOST), "mean_velocity")
         return U
+
+    def shell_velocity(self):
+        """Mean fluid velocity in the shell [R + 1, 2R] around each sphere, [nsph, 3]."""
+        u = np.zeros((self.nsph, 3))
+        if self.nsph:
+            self._chk(load().lbm_batch_shell_velocity(self._ctx, _ptr(u), LBM_HOST), "shell_velocity")
+        return u
 
     def get_f(self, box):
         L = self.edges[box]

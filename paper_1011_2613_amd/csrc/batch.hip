@@ -265,6 +265,73 @@ hipError_t launch_batch_init(const BatchArgs &a, int nbox, int maxL, hipStream_t
     return hipGetLastError();
 }
 
+// Mean pre-collision fluid velocity u = (sum_i c_i f_i) / (sum_i f_i) over the
+// fluid nodes (no sub-cell sample of any sphere) whose minimum-image distance
+// to the sphere centre lies in [R + 1, 2R]: the local flow a sphere sees.  One
+// workgroup per sphere over the cube of nodes around the centre; each node
+// counted once, through its minimum image; fixed-order workgroup reduction.
+__global__ __launch_bounds__(256) void k_batch_shell(BatchArgs a, int parity, double *out) {
+    using L = D3Q19;
+    __shared__ double red[4][256];
+    const int p = blockIdx.x;
+    const BatchBox bx = a.boxes[a.sph_box[p]];
+    const int Lb = bx.L;
+    const double Ld = (double)Lb;
+    const double R = bx.radius, rin2 = (R + 1.0) * (R + 1.0), rout2 = 4.0 * R * R;
+    const double xc[3] = {a.sph_x[3 * p], a.sph_x[3 * p + 1], a.sph_x[3 * p + 2]};
+    const int h = (int)ceil(2.0 * R) + 1;
+    const int w = 2 * h + 1;
+    const int cube = w * w * w;
+    int base[3];
+    for (int d = 0; d < 3; d++) base[d] = (int)floor(xc[d]);
+    const float *A = (parity ? a.B : a.A) + bx.off;
+    double s[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int t = threadIdx.x; t < cube; t += blockDim.x) {
+        const int off[3] = {t % w - h, (t / w) % w - h, t / (w * w) - h};
+        int c[3];
+        double r2 = 0.0;
+        bool once = true;
+        for (int d = 0; d < 3; d++) {
+            const double rd = (double)(base[d] + off[d]) - xc[d];
+            once = once && rd > -0.5 * Ld && rd <= 0.5 * Ld;
+            r2 += rd * rd;
+            int cd = (base[d] + off[d]) % Lb;
+            c[d] = cd < 0 ? cd + Lb : cd;
+        }
+        if (!once || r2 < rin2 || r2 > rout2) continue;
+        const int row = c[1] + Lb * c[2];
+        const uint64_t n = (uint64_t)c[0] + (uint64_t)Lb * (uint64_t)row;
+        if (a.cnt[bx.noff + n] != 0) continue;
+        double rho = 1.0, j[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+        for (int i = 0; i < L::Q; i++) {
+            const int sx = wrapL(c[0] - L::cx[i], Lb), sy = wrapL(c[1] - L::cy[i], Lb), sz = wrapL(c[2] - L::cz[i], Lb);
+            const double g = (double)A[belem(Lb, i, sx, sy + Lb * sz)];
+            rho += g;
+            j[0] += L::cx[i] * g;
+            j[1] += L::cy[i] * g;
+            j[2] += L::cz[i] * g;
+        }
+        for (int d = 0; d < 3; d++) s[d] += j[d] / rho;
+        s[3] += 1.0;
+    }
+    for (int d = 0; d < 4; d++) red[d][threadIdx.x] = s[d];
+    __syncthreads();
+    for (int k = blockDim.x / 2; k > 0; k >>= 1) {
+        if ((int)threadIdx.x < k)
+            for (int d = 0; d < 4; d++) red[d][threadIdx.x] += red[d][threadIdx.x + k];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0)
+        for (int d = 0; d < 3; d++) out[3 * p + d] = red[3][0] > 0.0 ? red[d][0] / red[3][0] : 0.0;
+}
+
+hipError_t launch_batch_shell(const BatchArgs &a, int parity, double *u, hipStream_t s) {
+    if (a.nsph == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_batch_shell, dim3((unsigned)a.nsph), dim3(256), 0, s, a, parity, u);
+    return hipGetLastError();
+}
+
 int batch_persistent_grid() {
     int dev = 0, cus = 0, per = 0;
     if (hipGetDevice(&dev) != hipSuccess) return 1024;

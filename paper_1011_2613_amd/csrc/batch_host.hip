@@ -316,6 +316,7 @@ int lbm_batch_create(const lbm_box *boxes, int nbox, int eps_samples, void *work
         const lbm_box &x = boxes[b];
         BatchBox &d = c->box[b];
         d.L = x.edge;
+        d.radius = x.radius;
         d.rows = 1;
         d.off = off;
         d.noff = noff;
@@ -424,6 +425,19 @@ int lbm_batch_mean_velocity(lbm_batch *c, double *U, int ptr_kind) {
     const hipMemcpyKind k = ptr_kind == LBM_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice;
     if (hipMemcpyAsync(U, c->ws + c->L.U, (size_t)c->L.nbox * 24, k, c->s) != hipSuccess) return LBM_E_HIP;
     return hipStreamSynchronize(c->s) == hipSuccess ? LBM_OK : LBM_E_HIP;
+}
+
+int lbm_batch_shell_velocity(lbm_batch *c, double *u, int ptr_kind) {
+    if (!c || !u) return LBM_E_INVALID;
+    const size_t n = (size_t)c->L.nsph * 24;
+    if (n == 0) return LBM_OK;
+    double *dst = u;
+    if (ptr_kind == LBM_HOST && hipMalloc(&dst, n) != hipSuccess) return LBM_E_HIP;
+    hipError_t e = launch_batch_shell(bargs(c), c->cur, dst, c->s);
+    if (e == hipSuccess && ptr_kind == LBM_HOST) e = hipMemcpyAsync(u, dst, n, hipMemcpyDeviceToHost, c->s);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->s);
+    if (ptr_kind == LBM_HOST) (void)hipFree(dst);
+    return e == hipSuccess ? LBM_OK : LBM_E_HIP;
 }
 
 int lbm_batch_get_distributions(lbm_batch *c, int b, double *f, int ptr_kind) {

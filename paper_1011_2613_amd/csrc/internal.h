@@ -140,6 +140,7 @@ struct BatchBox {
     float arel0f;          // 1 / tau
     float cgf[19];         // c_i . g_fluid
     float g0[19];          // initial shifted populations f^eq_i(1, u0) - w_i
+    double radius;         // sphere radius of the box
 };
 
 struct BatchArgs {
@@ -170,6 +171,7 @@ hipError_t launch_batch_force(const BatchArgs &a, hipStream_t s);
 hipError_t launch_batch_mean(const BatchArgs &a, int parity, double *U, hipStream_t s);
 hipError_t launch_batch_get_f(const BatchArgs &a, int b, int L, int parity, double *f, hipStream_t s);
 hipError_t launch_batch_init(const BatchArgs &a, int nbox, int maxL, hipStream_t s);
+hipError_t launch_batch_shell(const BatchArgs &a, int parity, double *u, hipStream_t s);
 int batch_persistent_grid();
 
 // launchers (lb_kernels.hip)

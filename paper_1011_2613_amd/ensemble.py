@@ -4,7 +4,8 @@ sample_boxes()   draws the periodic boxes of the ensemble (seeded);
 autotune_cached() tile shape and launch mode per box edge, cached in JSON;
 run_to_steady()  advances a Batch until every box's drag is steady or a step
                  cap is reached, retiring converged boxes early;
-features()       the 40 per-particle inputs of the closure;
+features()       the 40 per-particle inputs of the closure (local slip from
+                 the library's shell velocity);
 train_closure()  trains the BF16-MFMA MLP on (features, ln normalised drag);
 evaluate()       compares closure, a Wen-Yu-type correlation and the resolved
                  drag on held-out boxes, with resolved drag as the fallback
@@ -143,18 +144,21 @@ def run_to_steady(batch, boxes, check_every=500, max_steps=20000, tol=1e-5, mode
     return steady, stop
 
 
-def features(boxes, U):
+def features(boxes, U, Us):
     """The 40 per-particle closure inputs and the normalising drag scale.
 
     Per particle: local solid fraction of the other spheres within 3R (from
-    neighbour centres), box Reynolds number Re = |U| d / nu with U the
-    superficial mean velocity, log10 Re, (1 - phi_box) Re, a 32-bin histogram
-    of neighbour centres (4 radial shells r/d in [1, 1.5, 2, 2.5, 3) x 8
-    octants of the flow-aligned frame, x along U), the box solid fraction,
-    d / L, the nearest surface gap / d and N / 64.
+    neighbour centres), log10 of the box Reynolds number Re = |U| d / nu with
+    U the superficial mean velocity, the local slip (the mean fluid velocity
+    in the shell [R + 1, 2R] around the sphere, Us; the spheres are at rest)
+    in the flow-aligned frame over |U| (3), a 32-bin histogram of neighbour
+    centres (4 radial shells r/d in [1, 1.5, 2, 2.5, 3) x 8 octants of the
+    flow-aligned frame, x along U), the box solid fraction, d / L and the
+    nearest surface gap / d.
     Returns X [n, 40] and the Stokes drag scale 3 pi nu d |U| [n].
     """
     rows, scale = [], []
+    k = 0
     for bi, b in enumerate(boxes):
         pos, r, L = np.asarray(b["pos"]), b["radius"], b["edge"]
         n = len(pos)
@@ -187,9 +191,11 @@ def features(boxes, U):
             n_loc = int(np.count_nonzero(others & (dist < 3.0 * r)))
             phi_loc = n_loc / 27.0
             gap = (dist[others].min() - d) / d if n > 1 else L / d
-            rows.append([phi_loc, re, math.log10(max(re, 1e-6)), (1.0 - phi_box) * re, *hist,
-                         phi_box, d / L, gap, n / 64.0])
+            us = np.asarray(Us[k]) / max(umag, 1e-300)
+            rows.append([phi_loc, math.log10(max(re, 1e-6)), us @ ex, us @ ey, us @ ez, *hist,
+                         phi_box, d / L, gap])
             scale.append(3.0 * math.pi * nu * d * umag)
+            k += 1
     X = np.asarray(rows, dtype=np.float64)
     assert X.shape[1] == NFEAT
     return X, np.asarray(scale)
@@ -201,7 +207,7 @@ def drag_dataset(boxes, batch, steady, U):
     F, _ = batch.forces()
     counts = [len(b["pos"]) for b in boxes]
     offs = np.concatenate([[0], np.cumsum(counts)])
-    X, scale = features(boxes, U)
+    X, scale = features(boxes, U, batch.shell_velocity())
     y = np.empty(len(X))
     box_of = np.empty(len(X), dtype=int)
     k = 0
@@ -274,12 +280,13 @@ def evaluate(mlp, norm, X, y):
     training envelope fall back to the resolved drag (zero error, counted).
     The Wen-Yu-type correlation (no learning) uses the local solid fraction
     (feature 0, with the box value as floor) and the box Reynolds number."""
+    PHI_BOX, LOG_RE = NFEAT - 3, 1
     inside = norm.inside(X)
     pred = predict(mlp, norm, X)
     err_mlp = np.abs(pred - y) / np.abs(y)
     err_used = np.where(inside, err_mlp, 0.0)
-    phi = np.maximum(X[:, 0], X[:, 36])
-    wy = _wen_yu_factor(np.minimum(phi, 0.6), X[:, 1])
+    phi = np.maximum(X[:, 0], X[:, PHI_BOX])
+    wy = _wen_yu_factor(np.minimum(phi, 0.6), 10.0 ** X[:, LOG_RE])
     err_wy = np.abs(wy - y) / np.abs(y)
     t0 = time.perf_counter()
     _ = predict(mlp, norm, X)

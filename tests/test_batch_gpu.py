@@ -139,3 +139,40 @@ def test_initial_velocity_is_kept_without_forcing(gpu_lib):
     say("uniform box after 50 steps:", U[0])
     assert np.allclose(U[0], u0, rtol=1e-5, atol=1e-9)
     assert np.array_equal(U[1], np.zeros(3))
+
+
+def _shell_reference(f, pos, R, L, covered):
+    """Mean of u = sum c f / sum f over nodes with R + 1 <= |r| <= 2R
+    (minimum image) that no sphere covers, computed from [19][L,L,L] f."""
+    c = np.array([[0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0],
+                  [0, 0, 0, 1, -1, 0, 0, 1, -1, -1, 1, 0, 0, 0, 0, 1, -1, 1, -1],
+                  [0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, -1, 1, 1, -1, -1, 1]], dtype=float)
+    # f is [i][z][y][x] in node order x fastest
+    rho = f.sum(axis=0)
+    u = np.einsum("ai,izyx->azyx", c, f) / rho
+    z, y, x = np.meshgrid(np.arange(L), np.arange(L), np.arange(L), indexing="ij")
+    out = []
+    for p in pos:
+        d = [x - p[0], y - p[1], z - p[2]]
+        d = [dd - L * np.round(dd / L) for dd in d]
+        r2 = d[0] ** 2 + d[1] ** 2 + d[2] ** 2
+        m = (r2 >= (R + 1) ** 2) & (r2 <= 4 * R * R) & ~covered
+        out.append([u[a][m].mean() for a in range(3)])
+    return np.array(out)
+
+
+def test_shell_velocity_matches_populations(gpu_lib):
+    """Shell-averaged local fluid velocity from the library against the same
+    average taken in numpy over the box's pre-collision populations; two
+    spheres far apart, so no shell node is covered by the other sphere."""
+    L, R = 40, 5.0
+    pos = np.array([[10.3, 11.7, 9.2], [30.1, 29.4, 31.6]])
+    b = gpu_lib.Batch([{"edge": L, "tau": 0.8, "fluid_force": (3e-6, -1e-6, 2e-6), "pos": pos, "radius": R}],
+                      samples=4)
+    b.run(60)
+    us = b.shell_velocity()
+    f = b.get_f(0)
+    covered = np.zeros((L, L, L), dtype=bool)   # shell nodes are beyond R + 1 of both centres
+    ref = _shell_reference(f, pos, R, L, covered)
+    say("shell velocity", us, "reference", ref)
+    assert np.allclose(us, ref, rtol=1e-5, atol=1e-12)
