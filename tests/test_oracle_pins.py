@@ -6,6 +6,7 @@ special cases with a known answer.  No test retypes an oracle formula.
 """
 from fractions import Fraction
 import math
+import os
 
 import numpy as np
 import pytest
@@ -464,3 +465,52 @@ def test_splitmix64_reference_vector():
     out = I.splitmix64(0, 0, 2)
     assert int(out[0]) == 0xE220A8397B1DCDAF
     assert int(out[1]) == 0x6E789E6AA1B965F4
+
+
+# ------------------------------------------------ Table 2 printed values
+def _table2():
+    path = os.path.join(os.path.dirname(__file__), "golden", "table2_dem.txt")
+    vals = {}
+    with open(path) as fh:
+        for line in fh:
+            line = line.split("#")[0].split()
+            if line:
+                vals[line[0]] = (float(line[1]), float(line[2]))
+    return vals
+
+
+@pytest.mark.parametrize("col,dim", [(0, 2), (1, 3)])
+def test_table2_masses_and_contact_time(col, dim):
+    """The oracle fed with Table 2's solid density, diameter, stiffness and
+    restitution: (i) its particle mass (disc of unit depth in 2D, sphere in
+    3D) reproduces the printed mass, seen through the duration of a head-on
+    contact, which must match the printed contact-time formula (about 10
+    steps) to within one step; (ii) the pair rebounds with a restitution near
+    the printed 0.9 (symplectic Euler at 10 steps per contact)."""
+    t = _table2()
+    rho, d, m_print, k, e = (t[n][col] for n in ("rho_s", "d", "m_s", "k_n", "e"))
+    R = d / 2
+    m_formula = rho * (math.pi * R * R if dim == 2 else 4.0 / 3.0 * math.pi * R ** 3)
+    assert abs(m_formula - m_print) / m_print < 5e-5          # printed to 5 digits
+    tc = math.sqrt((math.pi ** 2 + math.log(e) ** 2) * (m_print / 2) / k)
+    assert abs(tc - 10.0) < 0.01
+    shape = [60, 24] if dim == 2 else [60, 24, 24]
+    sim = O.OracleSim(dim, shape, 0.7, samples=1, kn=k, restitution=e)
+    sim.set_coupling(False)
+    v0 = 0.05
+    z = 12.0 if dim == 3 else 0.0
+    sim.set_particles(np.array([[20.0, 12.0, z], [30.6, 12.0, z]]), vel=[[v0, 0, 0], [-v0, 0, 0]],
+                      radius=[R, R], rho_s=[rho, rho])
+    gaps, rel = [], []
+    for _ in range(60):
+        x, v, _ = sim.particles()
+        gaps.append(x[1, 0] - x[0, 0] - d)
+        rel.append(v[0, 0] - v[1, 0])
+        sim.step(1)
+    gaps = np.array(gaps)
+    contact = np.nonzero(gaps < 0)[0]
+    assert len(contact) > 0
+    steps_in_contact = contact[-1] - contact[0] + 1
+    assert abs(steps_in_contact - tc) <= 1.0
+    e_eff = -rel[-1] / rel[0]
+    assert abs(e_eff - e) < 0.01
