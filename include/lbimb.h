@@ -151,12 +151,15 @@ int64_t lbm_time(const lbm_ctx *ctx);
 /* Number of particles currently set (after lbm_set_particles or lbm_load). */
 int64_t lbm_particle_count(const lbm_ctx *ctx);
 
-/* Per-phase kernel timing.  While enabled, lbm_step launches the step kernels
- * one by one (no graph) with HIP events around each phase on the context's
- * stream; lbm_get_timing synchronises and returns the summed milliseconds and
- * the number of launches of each phase since timing was enabled.
- * Phases: 0 footprint (clear + paint), 1 lattice (stream-collide-IMB),
- * 2 hydrodynamic force, 3 cell list, 4 DEM contacts, 5 integration. */
+/* Per-phase kernel timing.  enable: 0 off, 1 every phase, 2 the lattice
+ * phase only (least perturbation of the step).  While enabled, lbm_step
+ * launches the step kernels one by one (no graph) with HIP events around the
+ * timed phases on the stream each phase runs on; lbm_get_timing synchronises
+ * and returns the summed milliseconds and the number of launches of each phase
+ * since timing was enabled.  Phases: 0 footprint, 1 lattice
+ * (stream-collide-IMB), 2 hydrodynamic force and integration, 3 cell list,
+ * 4 DEM contacts, 5 unused (integration runs inside phase 2).  Errors:
+ * LBM_E_INVALID for another `enable`. */
 #define LBM_NPHASES 6
 int lbm_set_timing(lbm_ctx *ctx, int enable);
 int lbm_get_timing(lbm_ctx *ctx, double *ms, int64_t *launches);

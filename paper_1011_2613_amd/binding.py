@@ -256,8 +256,9 @@ class Simulation:
         self._check(load().lbm_get_particles(self._ctx, _ptr(x), _ptr(v), _ptr(w), LBM_HOST))
         return x[: self.np_], v[: self.np_], w[: self.np_]
 
-    def set_timing(self, on):
-        self._check(load().lbm_set_timing(self._ctx, int(bool(on))))
+    def set_timing(self, on, lattice_only=False):
+        mode = 0 if not on else (2 if lattice_only else 1)
+        self._check(load().lbm_set_timing(self._ctx, mode))
 
     def get_timing(self):
         ms = (C.c_double * LBM_NPHASES)()

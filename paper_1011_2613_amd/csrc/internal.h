@@ -113,6 +113,8 @@ struct ForceArgs {
     Geom g;
     const QRec *qr;
     int D;
+    int integrate;         // 1: the kernel also advances the particle (needs F^c of this step)
+    double ap[3];          // particle acceleration (gravity with buoyancy)
 };
 
 struct CellArgs {
@@ -192,6 +194,5 @@ hipError_t launch_force(const ForceArgs &a, hipStream_t s);
 hipError_t launch_list_q(const ForceArgs &a, double *out, hipStream_t s);
 hipError_t launch_cells(const CellArgs &a, hipStream_t s);
 hipError_t launch_dem(const CellArgs &a, hipStream_t s);
-hipError_t launch_integrate(const CellArgs &a, hipStream_t s);
 
 }  // namespace lbimb

@@ -270,6 +270,16 @@ __global__ __launch_bounds__(256) void k_foot_paint(FootArgs a) {
     }
 }
 
+__device__ __forceinline__ double wrap_pos(double x, double L) {
+    if (x < 0.0) {
+        x = x + L;
+        if (x >= L) x = x - L;
+    } else if (x >= L) {
+        x = x - L;
+    }
+    return x;
+}
+
 // ------------------------------------------------- hydrodynamic force, Eq. 3
 struct Acc {
     double s, c;
@@ -297,7 +307,8 @@ __device__ __forceinline__ double shfl_xor_d(double v, int m) {
 
 // One workgroup per particle over its footprint list: each entry gives the
 // node and the particle's sample count there; q_n and the node's total count
-// come from the lattice kernel.  s_pn q_n and r_pn x (s_pn q_n) go into TwoSum
+// come from the lattice kernel.  With `integrate` set, the first thread then
+// advances the particle (the contact forces of the step are complete).  s_pn q_n and r_pn x (s_pn q_n) go into TwoSum
 // accumulators; each wavefront merges its lanes with butterfly shuffles and
 // the first thread merges the wavefronts in a fixed order.
 // F_p = -sum, T_p = -sum.
@@ -398,6 +409,7 @@ __global__ __launch_bounds__(256) void k_force(ForceArgs a) {
                 o.c = part[w][6 + 2 * d + 1];
                 acc_merge(T[d], o);
             }
+        double Fv[3], Tv[3];
         for (int d = 0; d < 3; d++) {
             double fv = -(F[d].s + F[d].c);
             double tv = -(T[d].s + T[d].c);
@@ -405,6 +417,28 @@ __global__ __launch_bounds__(256) void k_force(ForceArgs a) {
             if (D == 2 && d < 2) tv = 0.0;
             a.P.Fh[d * P + p] = fv;
             a.P.Th[d * P + p] = tv;
+            Fv[d] = fv;
+            Tv[d] = tv;
+        }
+        // Symplectic Euler with dt = 1 for this particle (every reader of its
+        // position in this kernel has read it): v += (F^h + F^c + m a)/m,
+        // omega += T^h/I, x += v (new), periodic wrap.
+        if (a.integrate && !a.P.fixed[p]) {
+            const double m = a.P.m[p];
+            for (int d = 0; d < D; d++) {
+                const double ftot = Fv[d] + a.P.Fc[d * P + p] + m * a.ap[d];
+                a.P.v[d * P + p] = a.P.v[d * P + p] + ftot / m;
+            }
+            if (D == 3) {
+                for (int d = 0; d < 3; d++) a.P.w[d * P + p] = a.P.w[d * P + p] + Tv[d] / a.P.I[p];
+            } else {
+                a.P.w[2 * P + p] = a.P.w[2 * P + p] + Tv[2] / a.P.I[p];
+            }
+            for (int d = 0; d < D; d++) {
+                double xn = a.P.x[d * P + p] + a.P.v[d * P + p];
+                if (!(d == 1 && a.g.wall_y)) xn = wrap_pos(xn, d == 0 ? a.g.Lx : (d == 1 ? a.g.Ly : a.g.Lz));
+                a.P.x[d * P + p] = xn;
+            }
         }
     }
 }
@@ -567,39 +601,6 @@ __global__ __launch_bounds__(256) void k_dem(CellArgs a) {
     }
 }
 
-__device__ __forceinline__ double wrap_pos(double x, double L) {
-    if (x < 0.0) {
-        x = x + L;
-        if (x >= L) x = x - L;
-    } else if (x >= L) {
-        x = x - L;
-    }
-    return x;
-}
-
-// Symplectic Euler with dt = 1: v += (F^h + F^c + m a)/m, omega += T^h/I,
-// x += v (new), periodic wrap.
-__global__ void k_integrate(CellArgs a) {
-    const int p = blockIdx.x * blockDim.x + threadIdx.x;
-    const int P = a.P.np;
-    if (p >= P || a.P.fixed[p]) return;
-    const int D = a.D;
-    const double m = a.P.m[p];
-    for (int d = 0; d < D; d++) {
-        const double ftot = a.P.Fh[d * P + p] + a.P.Fc[d * P + p] + m * a.ap[d];
-        a.P.v[d * P + p] = a.P.v[d * P + p] + ftot / m;
-    }
-    if (D == 3) {
-        for (int d = 0; d < 3; d++) a.P.w[d * P + p] = a.P.w[d * P + p] + a.P.Th[d * P + p] / a.P.I[p];
-    } else {
-        a.P.w[2 * P + p] = a.P.w[2 * P + p] + a.P.Th[2 * P + p] / a.P.I[p];
-    }
-    for (int d = 0; d < D; d++) {
-        double xn = a.P.x[d * P + p] + a.P.v[d * P + p];
-        if (!(d == 1 && a.g.wall_y)) xn = wrap_pos(xn, d == 0 ? a.g.Lx : (d == 1 ? a.g.Ly : a.g.Lz));
-        a.P.x[d * P + p] = xn;
-    }
-}
 
 // ---------------------------------------------------------------- launchers
 static unsigned blocks_for(int n, int per) { return (unsigned)((n + per - 1) / per); }
@@ -654,10 +655,5 @@ hipError_t launch_dem(const CellArgs &a, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_integrate(const CellArgs &a, hipStream_t s) {
-    if (a.P.np == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_integrate, dim3(blocks_for(a.P.np, 256)), dim3(256), 0, s, a);
-    return hipGetLastError();
-}
 
 }  // namespace lbimb

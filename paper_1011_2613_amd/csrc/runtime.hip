@@ -134,7 +134,8 @@ struct lbm_ctx {
     double cg[19];
     hipGraphExec_t graph[2];
     bool graph_ok[2];
-    bool timing;
+    int timing;  // 0 off, 1 every phase, 2 the lattice phase only
+    bool rec_open;
     std::vector<TimedEvent> events;
     size_t ev_used;
     double phase_ms[LBM_NPHASES];
@@ -242,7 +243,8 @@ LBArgs lb_args(lbm_ctx *c, int from) {
 
 // Phase markers for the timing mode.
 void phase_begin(lbm_ctx *c, int phase, hipStream_t s) {
-    if (!c->timing) return;
+    c->rec_open = c->timing == 1 || (c->timing == 2 && phase == 1);
+    if (!c->rec_open) return;
     if (c->ev_used == c->events.size()) {
         TimedEvent e{};
         (void)hipEventCreate(&e.a);
@@ -254,7 +256,8 @@ void phase_begin(lbm_ctx *c, int phase, hipStream_t s) {
 }
 
 void phase_end(lbm_ctx *c, hipStream_t s) {
-    if (!c->timing) return;
+    if (!c->rec_open) return;
+    c->rec_open = false;
     (void)hipEventRecord(c->events[c->ev_used].b, s);
     c->ev_used++;
 }
@@ -290,13 +293,12 @@ hipError_t enqueue_step(lbm_ctx *c, int from, hipStream_t s, int slot) {
         fo.g = c->g;
         fo.qr = wsp<QRec>(c, c->L.off_qr);
         fo.D = c->L.D;
+        fo.integrate = 1;
+        for (int d = 0; d < 3; d++) fo.ap[d] = c->cfg.particle_accel[d];
+        // the force kernel also integrates: it needs the contact forces
+        if ((e = hipStreamWaitEvent(s, c->ev_join[slot], 0)) != hipSuccess) return e;
         phase_begin(c, 2, s);
         if ((e = launch_force(fo, s)) != hipSuccess) return e;
-        phase_end(c, s);
-        if ((e = hipStreamWaitEvent(s, c->ev_join[slot], 0)) != hipSuccess) return e;
-        CellArgs ca = cell_args(c);
-        phase_begin(c, 5, s);
-        if ((e = launch_integrate(ca, s)) != hipSuccess) return e;
         phase_end(c, s);
     }
     return hipSuccess;
@@ -431,7 +433,8 @@ int lbm_create(const lbm_config *cfg, void *workspace, size_t ws_bytes, void *hi
         c->cg[i] = v;
     }
     c->graph_ok[0] = c->graph_ok[1] = false;
-    c->timing = false;
+    c->timing = 0;
+    c->rec_open = false;
     c->ev_used = 0;
     for (int k = 0; k < LBM_NPHASES; k++) { c->phase_ms[k] = 0.0; c->phase_n[k] = 0; }
     c->err[0] = 0;
@@ -709,6 +712,7 @@ int lbm_get_q(lbm_ctx *c, double *q, int ptr_kind) {
         fo.g = c->g;
         fo.qr = wsp<QRec>(c, c->L.off_qr);
         fo.D = c->L.D;
+        fo.integrate = 0;
         return launch_list_q(fo, (double *)dst, c->stream);
     });
 }
@@ -796,7 +800,8 @@ int lbm_step(lbm_ctx *c, int64_t nsteps) {
 int lbm_set_timing(lbm_ctx *c, int enable) {
     if (!c) return LBM_E_INVALID;
     HIPCHK(c, hipStreamSynchronize(c->stream));
-    c->timing = enable != 0;
+    if (enable < 0 || enable > 2) return LBM_E_INVALID;
+    c->timing = enable;
     c->ev_used = 0;
     for (int k = 0; k < LBM_NPHASES; k++) { c->phase_ms[k] = 0.0; c->phase_n[k] = 0; }
     return LBM_OK;
