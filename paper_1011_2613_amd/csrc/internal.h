@@ -79,6 +79,26 @@ struct alignas(32) QRec {
     int pad;
 };
 
+// The same record for the binary32 storage modes, whose q is computed in
+// binary32: 16 bytes, one aligned 16-byte store / load.
+struct alignas(16) QRec32 {
+    float q[3];
+    int tot;
+};
+
+// Reads q and the total count of node n from either record kind.
+__device__ __forceinline__ void read_qrec(const void *qr, bool r32, int64_t n, double q[3], int &tot) {
+    if (r32) {
+        const QRec32 r = ((const QRec32 *)qr)[n];
+        q[0] = (double)r.q[0]; q[1] = (double)r.q[1]; q[2] = (double)r.q[2];
+        tot = r.tot;
+    } else {
+        const QRec r = ((const QRec *)qr)[n];
+        q[0] = r.q[0]; q[1] = r.q[1]; q[2] = r.q[2];
+        tot = r.tot;
+    }
+}
+
 struct LBArgs {
     const void *A;         // post-collision populations of the previous step
     void *B;               // post-collision populations of this step
@@ -86,7 +106,7 @@ struct LBArgs {
     const uint32_t *slots; // [MAX_OWNERS][N] (pid << 10 | count)
     const double *beta_tab;   // beta(eps) for count 0..Smax
     const double *arel_tab;   // (1 - beta) / tau for count 0..Smax
-    QRec *qr;              // [N] IMB exchange records (covered nodes)
+    void *qr;              // [N] IMB exchange records (covered nodes): QRec (FP64) or QRec32
     const double *px, *pv, *pw;  // particle SoA
     int np;
     Geom g;
@@ -111,7 +131,8 @@ struct FootArgs {
 struct ForceArgs {
     Particles P;
     Geom g;
-    const QRec *qr;
+    const void *qr;        // QRec (FP64 storage) or QRec32 (binary32 storage modes)
+    int rec32;
     int D;
     int integrate;         // 1: the kernel also advances the particle (needs F^c of this step)
     double ap[3];          // particle acceleration (gravity with buoyancy)

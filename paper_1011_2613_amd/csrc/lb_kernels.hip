@@ -241,7 +241,7 @@ __device__ __forceinline__ void collide_f64(const LBArgs &a, uint64_t n, int x, 
         r.q[2] = L::D == 3 ? beta * mz : 0.0;
         r.tot = total;
         r.pad = 0;
-        a.qr[n] = r;
+        ((QRec *)a.qr)[n] = r;
         a.nown[n] = 0;  // the next footprint starts from zero counts
     }
 }
@@ -274,13 +274,12 @@ __device__ __forceinline__ void collide_shifted(const LBArgs &a, uint64_t n, int
     float mom[3];
     shifted_node<L, ST == 2>(gg, wave_fluid, beta, ar, (float)Vd[0], (float)Vd[1], (float)Vd[2], a.cgf, put, mom);
     if (nown != 0) {
-        QRec r;
-        r.q[0] = (double)mom[0];
-        r.q[1] = (double)mom[1];
-        r.q[2] = L::D == 3 ? (double)mom[2] : 0.0;
+        QRec32 r;
+        r.q[0] = mom[0];
+        r.q[1] = mom[1];
+        r.q[2] = L::D == 3 ? mom[2] : 0.0f;
         r.tot = total;
-        r.pad = 0;
-        a.qr[n] = r;
+        ((QRec32 *)a.qr)[n] = r;
         a.nown[n] = 0;  // the next footprint starts from zero counts
     }
 }

@@ -312,7 +312,7 @@ __device__ __forceinline__ double shfl_xor_d(double v, int m) {
 // accumulators; each wavefront merges its lanes with butterfly shuffles and
 // the first thread merges the wavefronts in a fixed order.
 // F_p = -sum, T_p = -sum.
-template <int D>
+template <int D, bool R32>
 __global__ __launch_bounds__(256) void k_force(ForceArgs a) {
     __shared__ double part[4][12];
     const int lane = threadIdx.x & 63;
@@ -348,11 +348,11 @@ __global__ __launch_bounds__(256) void k_force(ForceArgs a) {
             tot[u] = 1;
             if (v[u] != 0u) {
                 const int64_t n = (int64_t)ix[u] + (int64_t)a.g.nx * ((int64_t)iy[u] + (int64_t)a.g.ny * iz[u]);
-                const QRec r = a.qr[n];
-                q0[u] = r.q[0];
-                q1[u] = r.q[1];
-                q2[u] = r.q[2];
-                tot[u] = r.tot;
+                double qq[3];
+                read_qrec(a.qr, R32, n, qq, tot[u]);
+                q0[u] = qq[0];
+                q1[u] = qq[1];
+                q2[u] = qq[2];
             }
         }
 #pragma unroll
@@ -459,7 +459,10 @@ __global__ void k_list_q(ForceArgs a, double *out) {
         const int iy = wrap1(a.g, 1, lo1 + (int)((v >> 17) & 127u));
         const int iz = D == 3 ? wrap1(a.g, 2, lo2 + (int)((v >> 24) & 127u)) : 0;
         const int64_t n = (int64_t)ix + (int64_t)a.g.nx * ((int64_t)iy + (int64_t)a.g.ny * iz);
-        for (int d = 0; d < D; d++) out[d * N + n] = a.qr[n].q[d];
+        double qq[3];
+        int tot;
+        read_qrec(a.qr, a.rec32 != 0, n, qq, tot);
+        for (int d = 0; d < D; d++) out[d * N + n] = qq[d];
     }
 }
 
@@ -628,8 +631,14 @@ hipError_t launch_foot_paint(const FootArgs &a, int D, hipStream_t s) {
 
 hipError_t launch_force(const ForceArgs &a, hipStream_t s) {
     if (a.P.np == 0) return hipSuccess;
-    if (a.D == 2) hipLaunchKernelGGL(k_force<2>, dim3((unsigned)a.P.np), dim3(64), 0, s, a);
-    else hipLaunchKernelGGL(k_force<3>, dim3((unsigned)a.P.np), dim3(64), 0, s, a);
+    const dim3 g((unsigned)a.P.np), b(64);
+    if (a.D == 2) {
+        if (a.rec32) hipLaunchKernelGGL((k_force<2, true>), g, b, 0, s, a);
+        else hipLaunchKernelGGL((k_force<2, false>), g, b, 0, s, a);
+    } else {
+        if (a.rec32) hipLaunchKernelGGL((k_force<3, true>), g, b, 0, s, a);
+        else hipLaunchKernelGGL((k_force<3, false>), g, b, 0, s, a);
+    }
     return hipGetLastError();
 }
 

@@ -78,7 +78,7 @@ Layout make_layout(const lbm_config *c) {
     L.off_fB = take(fs);
     L.off_nown = take(((size_t)L.N + 3) / 4 * 4);
     L.off_slots = take((size_t)MAX_OWNERS * L.N * 4);
-    L.off_qr = take((size_t)L.N * sizeof(QRec));
+    L.off_qr = take((size_t)L.N * (c->storage == LBM_FP64 ? sizeof(QRec) : sizeof(QRec32)));
     L.off_beta = take((size_t)(L.Smax + 1) * 8);
     L.off_arel = take((size_t)(L.Smax + 1) * 8);
     const size_t P = (size_t)L.P;
@@ -223,7 +223,7 @@ LBArgs lb_args(lbm_ctx *c, int from) {
     a.slots = wsp<uint32_t>(c, c->L.off_slots);
     a.beta_tab = wsp<double>(c, c->L.off_beta);
     a.arel_tab = wsp<double>(c, c->L.off_arel);
-    a.qr = wsp<QRec>(c, c->L.off_qr);
+    a.qr = wsp<char>(c, c->L.off_qr);
     a.px = wsp<double>(c, c->L.off_x);
     a.pv = wsp<double>(c, c->L.off_v);
     a.pw = wsp<double>(c, c->L.off_w);
@@ -291,7 +291,8 @@ hipError_t enqueue_step(lbm_ctx *c, int from, hipStream_t s, int slot) {
         ForceArgs fo;
         fo.P = particles(c);
         fo.g = c->g;
-        fo.qr = wsp<QRec>(c, c->L.off_qr);
+        fo.qr = wsp<char>(c, c->L.off_qr);
+        fo.rec32 = c->cfg.storage != LBM_FP64;
         fo.D = c->L.D;
         fo.integrate = 1;
         for (int d = 0; d < 3; d++) fo.ap[d] = c->cfg.particle_accel[d];
@@ -474,7 +475,9 @@ int lbm_create(const lbm_config *cfg, void *workspace, size_t ws_bytes, void *hi
     chk(hipMemcpyAsync(wsp<double>(c, L.off_arel), arel.data(), arel.size() * 8, hipMemcpyHostToDevice, c->stream));
     chk(launch_fill_u32(wsp<uint32_t>(c, L.off_nown), 0u, (int64_t)((L.N + 3) / 4), c->stream));
     chk(launch_fill_u32(wsp<uint32_t>(c, L.off_flags), 0u, 16, c->stream));
-    chk(launch_fill_u32(wsp<uint32_t>(c, L.off_qr), 0u, (int64_t)L.N * (int64_t)(sizeof(QRec) / 4), c->stream));
+    chk(launch_fill_u32(wsp<uint32_t>(c, L.off_qr), 0u,
+                        (int64_t)L.N * (int64_t)((cfg->storage == LBM_FP64 ? sizeof(QRec) : sizeof(QRec32)) / 4),
+                        c->stream));
     // fluid at rest: f = f^eq(1, 0) = w_i  (shifted storage: g = 0)
     {
         const int Q = L.Q;
@@ -710,7 +713,8 @@ int lbm_get_q(lbm_ctx *c, double *q, int ptr_kind) {
         ForceArgs fo;
         fo.P = particles(c);
         fo.g = c->g;
-        fo.qr = wsp<QRec>(c, c->L.off_qr);
+        fo.qr = wsp<char>(c, c->L.off_qr);
+        fo.rec32 = c->cfg.storage != LBM_FP64;
         fo.D = c->L.D;
         fo.integrate = 0;
         return launch_list_q(fo, (double *)dst, c->stream);

@@ -164,22 +164,29 @@ def test_pure_fluid_no_particles(gpu_lib):
 
 # ----------------------------------------------------------- runtime paths
 def test_graph_and_eager_agree_bitwise(gpu_lib):
-    """Graph replay (timing off) and one-by-one launches (timing on) give the
-    same state bit for bit; two runs are identical (no races)."""
+    """Graph replay (timing off) and one-by-one launches (every phase timed,
+    or the lattice phase only) give the same state bit for bit; two runs are
+    identical (no races)."""
     w, parts = c1_particles()
     say("graph vs eager")
     sims = []
-    for timing in (False, True, False):
+    for timing, lat_only in ((False, False), (True, False), (False, False), (True, True)):
         s = gpu_lib.Simulation(2, w.shape, w.tau, fluid_force=w.fluid_force, samples=w.samples,
                                kn=w.kn, restitution=w.restitution, max_particles=16)
         s.set_particles(*parts)
-        s.set_timing(timing)
+        s.set_timing(timing, lattice_only=lat_only)
         s.step(37)
         sims.append(s)
     f = [s.get_f() for s in sims]
-    assert np.array_equal(f[0], f[1]) and np.array_equal(f[0], f[2])
+    x = [s.particles()[0] for s in sims]
+    for k in (1, 2, 3):
+        assert np.array_equal(f[0], f[k]) and np.array_equal(x[0], x[k])
     t = sims[1].get_timing()
     assert t["lattice"][1] == 37 and t["lattice"][0] > 0
+    assert t["footprint"][1] == 37 and t["force"][1] == 37 and t["dem"][1] == 37
+    t = sims[3].get_timing()   # lattice-only mode: no other phase is timed
+    assert t["lattice"][1] == 37 and t["lattice"][0] > 0
+    assert all(n == 0 for k, (ms, n) in t.items() if k != "lattice")
 
 
 def test_save_load_resume_bitwise(gpu_lib):
