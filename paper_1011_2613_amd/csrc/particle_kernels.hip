@@ -240,20 +240,56 @@ __global__ __launch_bounds__(256) void k_foot_paint(FootArgs a) {
                                                     D == 3 ? ndisp(a.g, 2, iz, xp2) : 0.0, R2);
         }
         __syncthreads();
-        // (C) list positions in node order, owner slots, list entries
+        // (C) list positions in node order, owner slots, list entries.  The
+        // covered nodes of a wavefront that fall in one aligned 8-byte word of
+        // the owner counts sit in consecutive lanes (x fastest); the first
+        // lane of such a run claims all of them with one 64-bit atomic add and
+        // every lane of the run reads its own byte of the returned word, which
+        // is what one atomic add per node in lane order would have returned.
+        const int lane = threadIdx.x & 63;
         for (int i0 = 0; i0 < nc; i0 += blockDim.x) {
             const int i = i0 + threadIdx.x;
             const int count = i < nc ? (int)s_cnt[i] : 0;
             int total;
             const int pos = base + block_scan(count > 0 ? 1 : 0, total);
+            int kx = 0, ky = 0, kz = 0;
+            int64_t n = 0;
+            long long key = -1;  // owner-count word of a covered node
             if (count > 0) {
-                int kx, ky, kz, ix, iy, iz;
+                int ix, iy, iz;
                 node_of(c0 + i, kx, ky, kz, ix, iy, iz);
-                const int64_t n = (int64_t)ix + (int64_t)a.g.nx * ((int64_t)iy + (int64_t)a.g.ny * iz);
-                uint32_t *word = (uint32_t *)(a.nown + (n & ~(int64_t)3));
-                const int sh = 8 * (int)(n & 3);
-                const uint32_t old = atomicAdd(word, 1u << sh);
-                const int slot = (int)((old >> sh) & 0xffu);
+                n = (int64_t)ix + (int64_t)a.g.nx * ((int64_t)iy + (int64_t)a.g.ny * iz);
+                key = (long long)(n >> 3);
+            }
+            const int byte = (int)(n & 7);
+            uint32_t mask = key >= 0 ? 1u << byte : 0u;
+            int back = 0;  // lanes between this one and the first of its run
+            bool run = true;
+#pragma unroll
+            for (int j = 1; j < 8; j++) {
+                const long long kj = __shfl_up(key, j, 64);
+                run = run && lane >= j && kj == key;
+                back += run ? 1 : 0;
+            }
+            run = true;
+#pragma unroll
+            for (int j = 1; j < 8; j++) {
+                const long long kj = __shfl_down(key, j, 64);
+                const uint32_t mj = __shfl_down(mask, j, 64);
+                run = run && lane + j < 64 && kj == key;
+                if (run) mask |= mj;
+            }
+            unsigned long long old = 0ull;
+            if (key >= 0 && back == 0) {
+                unsigned long long inc = 0ull;
+#pragma unroll
+                for (int q = 0; q < 8; q++)
+                    if ((mask >> q) & 1u) inc |= 1ull << (8 * q);
+                old = atomicAdd((unsigned long long *)(a.nown + ((int64_t)key << 3)), inc);
+            }
+            old = __shfl(old, lane - back, 64);
+            if (count > 0) {
+                const int slot = (int)((old >> (8 * byte)) & 0xffull);
                 if (slot < MAX_OWNERS)
                     a.slots[(int64_t)slot * N + n] = ((uint32_t)p << SLOT_COUNT_BITS) | (uint32_t)count;
                 else

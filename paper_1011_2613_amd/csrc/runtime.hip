@@ -76,7 +76,9 @@ Layout make_layout(const lbm_config *c) {
     auto take = [&](size_t bytes) { size_t r = o; o = align_up(o + bytes); return r; };
     L.off_fA = take(fs);
     L.off_fB = take(fs);
-    L.off_nown = take(((size_t)L.N + 3) / 4 * 4);
+    // whole aligned 8-byte words: the footprint kernel claims owner slots
+    // with 64-bit atomic adds
+    L.off_nown = take(((size_t)L.N + 7) / 8 * 8);
     L.off_slots = take((size_t)MAX_OWNERS * L.N * 4);
     L.off_qr = take((size_t)L.N * (c->storage == LBM_FP64 ? sizeof(QRec) : sizeof(QRec32)));
     L.off_beta = take((size_t)(L.Smax + 1) * 8);
@@ -283,6 +285,11 @@ hipError_t enqueue_step(lbm_ctx *c, int from, hipStream_t s, int slot) {
         phase_begin(c, 0, s);
         if ((e = launch_foot_paint(fa, c->L.D, s)) != hipSuccess) return e;
         phase_end(c, s);
+        // contact forces are needed by the force kernel (integration); the
+        // join sits before the lattice kernel, by when the cell list and the
+        // contacts (shorter than the footprint) are done, so no wait sits
+        // between the lattice and force kernels
+        if ((e = hipStreamWaitEvent(s, c->ev_join[slot], 0)) != hipSuccess) return e;
     }
     phase_begin(c, 1, s);
     if ((e = launch_lb(lattice, storage, lb_args(c, from), s)) != hipSuccess) return e;
@@ -296,8 +303,6 @@ hipError_t enqueue_step(lbm_ctx *c, int from, hipStream_t s, int slot) {
         fo.D = c->L.D;
         fo.integrate = 1;
         for (int d = 0; d < 3; d++) fo.ap[d] = c->cfg.particle_accel[d];
-        // the force kernel also integrates: it needs the contact forces
-        if ((e = hipStreamWaitEvent(s, c->ev_join[slot], 0)) != hipSuccess) return e;
         phase_begin(c, 2, s);
         if ((e = launch_force(fo, s)) != hipSuccess) return e;
         phase_end(c, s);
@@ -473,7 +478,7 @@ int lbm_create(const lbm_config *cfg, void *workspace, size_t ws_bytes, void *hi
     auto chk = [&](hipError_t e) { if (e != hipSuccess && r == LBM_OK) r = fail(c, LBM_E_HIP, "%s", hipGetErrorString(e)); };
     chk(hipMemcpyAsync(wsp<double>(c, L.off_beta), beta.data(), beta.size() * 8, hipMemcpyHostToDevice, c->stream));
     chk(hipMemcpyAsync(wsp<double>(c, L.off_arel), arel.data(), arel.size() * 8, hipMemcpyHostToDevice, c->stream));
-    chk(launch_fill_u32(wsp<uint32_t>(c, L.off_nown), 0u, (int64_t)((L.N + 3) / 4), c->stream));
+    chk(launch_fill_u32(wsp<uint32_t>(c, L.off_nown), 0u, (int64_t)((L.N + 7) / 8 * 2), c->stream));
     chk(launch_fill_u32(wsp<uint32_t>(c, L.off_flags), 0u, 16, c->stream));
     chk(launch_fill_u32(wsp<uint32_t>(c, L.off_qr), 0u,
                         (int64_t)L.N * (int64_t)((cfg->storage == LBM_FP64 ? sizeof(QRec) : sizeof(QRec32)) / 4),
@@ -647,7 +652,7 @@ int lbm_set_particles(lbm_ctx *c, int64_t n, const double *pos, const double *ve
     HIPCHK(c, hipMemcpy(wsp<uint8_t>(c, c->L.off_fixed), F.data(), np, hipMemcpyHostToDevice));
     c->ncx = nc[0]; c->ncy = nc[1]; c->ncz = nc[2];
     // forget the old footprint, then record bounding boxes for the first clear
-    HIPCHK(c, launch_fill_u32(wsp<uint32_t>(c, c->L.off_nown), 0u, (int64_t)((c->L.N + 3) / 4), c->stream));
+    HIPCHK(c, launch_fill_u32(wsp<uint32_t>(c, c->L.off_nown), 0u, (int64_t)((c->L.N + 7) / 8 * 2), c->stream));
     HIPCHK(c, launch_fill_u32(wsp<uint32_t>(c, c->L.off_Fh), 0u, (int64_t)(3 * np * 2), c->stream));
     HIPCHK(c, launch_fill_u32(wsp<uint32_t>(c, c->L.off_Th), 0u, (int64_t)(3 * np * 2), c->stream));
     HIPCHK(c, launch_fill_u32(wsp<uint32_t>(c, c->L.off_Fc), 0u, (int64_t)(3 * np * 2), c->stream));
@@ -900,7 +905,7 @@ int lbm_load(lbm_ctx *c, const char *path) {
     c->cur = 0;
     c->t = t;
     c->particles_set = true;
-    HIPCHK(c, launch_fill_u32(wsp<uint32_t>(c, c->L.off_nown), 0u, (int64_t)((c->L.N + 3) / 4), c->stream));
+    HIPCHK(c, launch_fill_u32(wsp<uint32_t>(c, c->L.off_nown), 0u, (int64_t)((c->L.N + 7) / 8 * 2), c->stream));
     HIPCHK(c, launch_fill_u32(wsp<uint32_t>(c, c->L.off_list_len), 0u, (int64_t)std::max(np, 1), c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     return LBM_OK;
