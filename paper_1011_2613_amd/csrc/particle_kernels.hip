@@ -80,12 +80,15 @@ __device__ __forceinline__ int sample_count(double d0, double d1, double d2, dou
     } else {
         if (mnx + mny + mnz > R2) return 0;
         if (mxx + mxy + mxz <= R2) return S * S * S;
+        // kz innermost: one partial sum sx + sy live at a time
 #pragma unroll
-        for (int kz = 0; kz < S; kz++)
+        for (int ky = 0; ky < S; ky++)
 #pragma unroll
-            for (int ky = 0; ky < S; ky++)
+            for (int kx = 0; kx < S; kx++) {
+                const double t = sx[kx] + sy[ky];
 #pragma unroll
-                for (int kx = 0; kx < S; kx++) count += (sx[kx] + sy[ky] + sz[kz] <= R2) ? 1 : 0;
+                for (int kz = 0; kz < S; kz++) count += (t + sz[kz] <= R2) ? 1 : 0;
+            }
     }
     return count;
 }
@@ -167,8 +170,8 @@ __device__ __forceinline__ int classify(double d0, double d1, double d2, double 
 // fastest), a workgroup prefix sum over covered nodes gives each its place in
 // the particle's list, and the thread claims an owner slot and writes the
 // entry, so the list is the same on every run.
-template <int D, int S>
-__global__ __launch_bounds__(256) void k_foot_paint(FootArgs a) {
+template <int D, int S, int NT>
+__global__ __launch_bounds__(NT) void k_foot_paint(FootArgs a) {
     constexpr int CHUNK = 1024;
     __shared__ uint16_t s_cnt[CHUNK];
     __shared__ uint16_t s_todo[CHUNK];
@@ -219,7 +222,8 @@ __global__ __launch_bounds__(256) void k_foot_paint(FootArgs a) {
         if (threadIdx.x == 0) s_ntodo = 0;
         __syncthreads();
         // (A) classify
-        for (int i = threadIdx.x; i < nc; i += blockDim.x) {
+#pragma unroll 1
+        for (int i = threadIdx.x; i < nc; i += NT) {
             int kx, ky, kz, ix, iy, iz;
             node_of(c0 + i, kx, ky, kz, ix, iy, iz);
             int cls = 0;
@@ -232,7 +236,8 @@ __global__ __launch_bounds__(256) void k_foot_paint(FootArgs a) {
         __syncthreads();
         // (B) exact per-sample counts of the undecided nodes
         const int ntodo = s_ntodo;
-        for (int j = threadIdx.x; j < ntodo; j += blockDim.x) {
+#pragma unroll 1
+        for (int j = threadIdx.x; j < ntodo; j += NT) {
             const int i = s_todo[j];
             int kx, ky, kz, ix, iy, iz;
             node_of(c0 + i, kx, ky, kz, ix, iy, iz);
@@ -240,63 +245,79 @@ __global__ __launch_bounds__(256) void k_foot_paint(FootArgs a) {
                                                     D == 3 ? ndisp(a.g, 2, iz, xp2) : 0.0, R2);
         }
         __syncthreads();
-        // (C) list positions in node order, owner slots, list entries.  The
-        // covered nodes of a wavefront that fall in one aligned 8-byte word of
-        // the owner counts sit in consecutive lanes (x fastest); the first
-        // lane of such a run claims all of them with one 64-bit atomic add and
-        // every lane of the run reads its own byte of the returned word, which
-        // is what one atomic add per node in lane order would have returned.
-        const int lane = threadIdx.x & 63;
-        for (int i0 = 0; i0 < nc; i0 += blockDim.x) {
-            const int i = i0 + threadIdx.x;
-            const int count = i < nc ? (int)s_cnt[i] : 0;
-            int total;
-            const int pos = base + block_scan(count > 0 ? 1 : 0, total);
-            int kx = 0, ky = 0, kz = 0;
-            int64_t n = 0;
-            long long key = -1;  // owner-count word of a covered node
-            if (count > 0) {
-                int ix, iy, iz;
-                node_of(c0 + i, kx, ky, kz, ix, iy, iz);
-                n = (int64_t)ix + (int64_t)a.g.nx * ((int64_t)iy + (int64_t)a.g.ny * iz);
-                key = (long long)(n >> 3);
-            }
-            const int byte = (int)(n & 7);
-            uint32_t mask = key >= 0 ? 1u << byte : 0u;
-            int back = 0;  // lanes between this one and the first of its run
-            bool run = true;
+        // (C1) the covered nodes of the chunk in node order into s_todo (the
+        // queue of (B) is spent): each thread takes PER consecutive nodes, one
+        // workgroup prefix sum places them
+        {
+            constexpr int PER = CHUNK / NT;
+            const int j0 = (int)threadIdx.x * PER;
+            int m = 0;
 #pragma unroll
-            for (int j = 1; j < 8; j++) {
-                const long long kj = __shfl_up(key, j, 64);
-                run = run && lane >= j && kj == key;
-                back += run ? 1 : 0;
-            }
-            run = true;
+            for (int u = 0; u < PER; u++) m += (j0 + u < nc && s_cnt[j0 + u] > 0) ? 1 : 0;
+            int ncov;
+            int at = block_scan(m, ncov);
 #pragma unroll
-            for (int j = 1; j < 8; j++) {
-                const long long kj = __shfl_down(key, j, 64);
-                const uint32_t mj = __shfl_down(mask, j, 64);
-                run = run && lane + j < 64 && kj == key;
-                if (run) mask |= mj;
-            }
-            unsigned long long old = 0ull;
-            if (key >= 0 && back == 0) {
-                unsigned long long inc = 0ull;
+            for (int u = 0; u < PER; u++)
+                if (j0 + u < nc && s_cnt[j0 + u] > 0) s_todo[at++] = (uint16_t)(j0 + u);
+            __syncthreads();
+            // (C2) owner slots and list entries, k-th covered node in lane
+            // order.  Covered nodes that fall in one aligned 8-byte word of the
+            // owner counts sit in consecutive lanes; the first lane of such a
+            // run claims all of them with one 64-bit atomic add and every lane
+            // of the run reads its own byte of the returned word, which is what
+            // one atomic add per node in lane order would have returned.
+            const int lane = threadIdx.x & 63;
+#pragma unroll 1
+            for (int k0 = 0; k0 < ncov; k0 += NT) {
+                const int k = k0 + (int)threadIdx.x;
+                int count = 0, kx = 0, ky = 0, kz = 0;
+                int64_t n = 0;
+                long long key = -1;  // owner-count word of a covered node
+                if (k < ncov) {
+                    const int i = s_todo[k];
+                    count = s_cnt[i];
+                    int ix, iy, iz;
+                    node_of(c0 + i, kx, ky, kz, ix, iy, iz);
+                    n = (int64_t)ix + (int64_t)a.g.nx * ((int64_t)iy + (int64_t)a.g.ny * iz);
+                    key = (long long)(n >> 3);
+                }
+                const int byte = (int)(n & 7);
+                uint32_t mask = key >= 0 ? 1u << byte : 0u;
+                int back = 0;  // lanes between this one and the first of its run
+                bool run = true;
 #pragma unroll
-                for (int q = 0; q < 8; q++)
-                    if ((mask >> q) & 1u) inc |= 1ull << (8 * q);
-                old = atomicAdd((unsigned long long *)(a.nown + ((int64_t)key << 3)), inc);
+                for (int j = 1; j < 8; j++) {
+                    const long long kj = __shfl_up(key, j, 64);
+                    run = run && lane >= j && kj == key;
+                    back += run ? 1 : 0;
+                }
+                run = true;
+#pragma unroll
+                for (int j = 1; j < 8; j++) {
+                    const long long kj = __shfl_down(key, j, 64);
+                    const uint32_t mj = __shfl_down(mask, j, 64);
+                    run = run && lane + j < 64 && kj == key;
+                    if (run) mask |= mj;
+                }
+                unsigned long long old = 0ull;
+                if (key >= 0 && back == 0) {
+                    unsigned long long inc = 0ull;
+#pragma unroll
+                    for (int q = 0; q < 8; q++)
+                        if ((mask >> q) & 1u) inc |= 1ull << (8 * q);
+                    old = atomicAdd((unsigned long long *)(a.nown + ((int64_t)key << 3)), inc);
+                }
+                old = __shfl(old, lane - back, 64);
+                if (k < ncov) {
+                    const int slot = (int)((old >> (8 * byte)) & 0xffull);
+                    if (slot < MAX_OWNERS)
+                        a.slots[(int64_t)slot * N + n] = ((uint32_t)p << SLOT_COUNT_BITS) | (uint32_t)count;
+                    else
+                        atomicOr(a.flags, FLAG_SLOT_OVERFLOW);
+                    if (base + k < cap) list[base + k] = list_entry(count, kx, ky, kz);
+                }
             }
-            old = __shfl(old, lane - back, 64);
-            if (count > 0) {
-                const int slot = (int)((old >> (8 * byte)) & 0xffull);
-                if (slot < MAX_OWNERS)
-                    a.slots[(int64_t)slot * N + n] = ((uint32_t)p << SLOT_COUNT_BITS) | (uint32_t)count;
-                else
-                    atomicOr(a.flags, FLAG_SLOT_OVERFLOW);
-                if (pos < cap) list[pos] = list_entry(count, kx, ky, kz);
-            }
-            base += total;
+            base += ncov;
         }
         __syncthreads();
     }
@@ -644,25 +665,25 @@ __global__ __launch_bounds__(256) void k_dem(CellArgs a) {
 // ---------------------------------------------------------------- launchers
 static unsigned blocks_for(int n, int per) { return (unsigned)((n + per - 1) / per); }
 
-template <int D>
-static hipError_t paint_s(const FootArgs &a, hipStream_t s, int block) {
-    const dim3 g((unsigned)a.P.np), b((unsigned)block);
+template <int D, int NT>
+static hipError_t paint_s(const FootArgs &a, hipStream_t s) {
+    const dim3 g((unsigned)a.P.np), b((unsigned)NT);
     switch (a.S) {
-        case 1: hipLaunchKernelGGL((k_foot_paint<D, 1>), g, b, 0, s, a); break;
-        case 2: hipLaunchKernelGGL((k_foot_paint<D, 2>), g, b, 0, s, a); break;
-        case 3: hipLaunchKernelGGL((k_foot_paint<D, 3>), g, b, 0, s, a); break;
-        case 4: hipLaunchKernelGGL((k_foot_paint<D, 4>), g, b, 0, s, a); break;
-        case 5: hipLaunchKernelGGL((k_foot_paint<D, 5>), g, b, 0, s, a); break;
-        case 6: hipLaunchKernelGGL((k_foot_paint<D, 6>), g, b, 0, s, a); break;
-        case 7: hipLaunchKernelGGL((k_foot_paint<D, 7>), g, b, 0, s, a); break;
-        default: hipLaunchKernelGGL((k_foot_paint<D, 8>), g, b, 0, s, a); break;
+        case 1: hipLaunchKernelGGL((k_foot_paint<D, 1, NT>), g, b, 0, s, a); break;
+        case 2: hipLaunchKernelGGL((k_foot_paint<D, 2, NT>), g, b, 0, s, a); break;
+        case 3: hipLaunchKernelGGL((k_foot_paint<D, 3, NT>), g, b, 0, s, a); break;
+        case 4: hipLaunchKernelGGL((k_foot_paint<D, 4, NT>), g, b, 0, s, a); break;
+        case 5: hipLaunchKernelGGL((k_foot_paint<D, 5, NT>), g, b, 0, s, a); break;
+        case 6: hipLaunchKernelGGL((k_foot_paint<D, 6, NT>), g, b, 0, s, a); break;
+        case 7: hipLaunchKernelGGL((k_foot_paint<D, 7, NT>), g, b, 0, s, a); break;
+        default: hipLaunchKernelGGL((k_foot_paint<D, 8, NT>), g, b, 0, s, a); break;
     }
     return hipGetLastError();
 }
 
 hipError_t launch_foot_paint(const FootArgs &a, int D, hipStream_t s) {
     if (a.P.np == 0) return hipSuccess;
-    return D == 2 ? paint_s<2>(a, s, 128) : paint_s<3>(a, s, 256);
+    return D == 2 ? paint_s<2, 128>(a, s) : paint_s<3, 256>(a, s);
 }
 
 hipError_t launch_force(const ForceArgs &a, hipStream_t s) {
