@@ -378,21 +378,41 @@ __global__ __launch_bounds__(256) void k_force(ForceArgs a) {
     const int p = blockIdx.x;
     const int P = a.P.np;
     const int len = a.P.list_len[p];
+    const int cap = a.P.list_cap;
     const int lo0 = a.P.bb[p], lo1 = a.P.bb[P + p], lo2 = a.P.bb[2 * P + p];
-    const uint32_t *list = a.P.list + (int64_t)p * a.P.list_cap;
+    const uint32_t *list = a.P.list + (int64_t)p * cap;
     const double xp0 = a.P.x[p], xp1 = a.P.x[P + p], xp2 = D == 3 ? a.P.x[2 * P + p] : 0.0;
+    // the integration inputs, one per lane (v, omega, F^c, m, I, fixed),
+    // loaded beside the sums and gathered by the first thread at the end
+    double pre = 0.0;
+    if (a.integrate && lane < 12) {
+        if (lane < 3) pre = a.P.v[lane * P + p];
+        else if (lane < 6) pre = a.P.w[(lane - 3) * P + p];
+        else if (lane < 9) pre = a.P.Fc[(lane - 6) * P + p];
+        else if (lane == 9) pre = a.P.m[p];
+        else if (lane == 10) pre = a.P.I[p];
+        else pre = a.P.fixed[p] ? 1.0 : 0.0;
+    }
     Acc F[3] = {{0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}};
     Acc T[3] = {{0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}};
-    // UN entries per thread per round: all list and q loads of a round are
-    // issued before the first accumulation, so a round costs two memory
-    // latencies instead of two per entry.
+    // UN entries per thread per round: all q loads of a round are issued
+    // before the first accumulation, and the list entries of the next round
+    // are loaded while they are in flight (the first round's beside the list
+    // length: loads below the capacity stay inside the particle's list).
     constexpr int UN = 4;
-    for (int e0 = 0; e0 < len; e0 += UN * (int)blockDim.x) {
+    const int stride = UN * (int)blockDim.x;
+    uint32_t vn[UN];
+#pragma unroll
+    for (int u = 0; u < UN; u++) {
+        const int e = u * (int)blockDim.x + (int)threadIdx.x;
+        vn[u] = e < cap ? list[e] : 0u;
+    }
+    for (int e0 = 0; e0 < len; e0 += stride) {
         uint32_t v[UN];
 #pragma unroll
         for (int u = 0; u < UN; u++) {
             const int e = e0 + u * (int)blockDim.x + (int)threadIdx.x;
-            v[u] = e < len ? list[e] : 0u;
+            v[u] = e < len ? vn[u] : 0u;
         }
         double q0[UN], q1[UN], q2[UN];
         int tot[UN], ix[UN], iy[UN], iz[UN];
@@ -411,6 +431,11 @@ __global__ __launch_bounds__(256) void k_force(ForceArgs a) {
                 q1[u] = qq[1];
                 q2[u] = qq[2];
             }
+        }
+#pragma unroll
+        for (int u = 0; u < UN; u++) {
+            const int e = e0 + stride + u * (int)blockDim.x + (int)threadIdx.x;
+            vn[u] = e < len ? list[e] : 0u;
         }
 #pragma unroll
         for (int u = 0; u < UN; u++) {
@@ -455,6 +480,13 @@ __global__ __launch_bounds__(256) void k_force(ForceArgs a) {
             part[wave][6 + 2 * d + 1] = T[d].c;
         }
     __syncthreads();
+    double pv[3], pw[3], pfc[3];
+    for (int d = 0; d < 3; d++) {
+        pv[d] = __shfl(pre, d, 64);
+        pw[d] = __shfl(pre, 3 + d, 64);
+        pfc[d] = __shfl(pre, 6 + d, 64);
+    }
+    const double pm = __shfl(pre, 9, 64), pI = __shfl(pre, 10, 64), pfix = __shfl(pre, 11, 64);
     if (threadIdx.x == 0) {
         for (int w = 1; w < nw; w++)
             for (int d = 0; d < 3; d++) {
@@ -480,21 +512,20 @@ __global__ __launch_bounds__(256) void k_force(ForceArgs a) {
         // Symplectic Euler with dt = 1 for this particle (every reader of its
         // position in this kernel has read it): v += (F^h + F^c + m a)/m,
         // omega += T^h/I, x += v (new), periodic wrap.
-        if (a.integrate && !a.P.fixed[p]) {
-            const double m = a.P.m[p];
+        if (a.integrate && pfix == 0.0) {
+            const double xo[3] = {xp0, xp1, xp2};
             for (int d = 0; d < D; d++) {
-                const double ftot = Fv[d] + a.P.Fc[d * P + p] + m * a.ap[d];
-                a.P.v[d * P + p] = a.P.v[d * P + p] + ftot / m;
-            }
-            if (D == 3) {
-                for (int d = 0; d < 3; d++) a.P.w[d * P + p] = a.P.w[d * P + p] + Tv[d] / a.P.I[p];
-            } else {
-                a.P.w[2 * P + p] = a.P.w[2 * P + p] + Tv[2] / a.P.I[p];
-            }
-            for (int d = 0; d < D; d++) {
-                double xn = a.P.x[d * P + p] + a.P.v[d * P + p];
+                const double ftot = Fv[d] + pfc[d] + pm * a.ap[d];
+                const double vn = pv[d] + ftot / pm;
+                a.P.v[d * P + p] = vn;
+                double xn = xo[d] + vn;
                 if (!(d == 1 && a.g.wall_y)) xn = wrap_pos(xn, d == 0 ? a.g.Lx : (d == 1 ? a.g.Ly : a.g.Lz));
                 a.P.x[d * P + p] = xn;
+            }
+            if (D == 3) {
+                for (int d = 0; d < 3; d++) a.P.w[d * P + p] = pw[d] + Tv[d] / pI;
+            } else {
+                a.P.w[2 * P + p] = pw[2] + Tv[2] / pI;
             }
         }
     }
