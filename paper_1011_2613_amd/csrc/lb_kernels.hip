@@ -110,6 +110,62 @@ __device__ __forceinline__ int solid_velocity(const LBArgs &a, int64_t n, int no
     return total;
 }
 
+// The same in binary32 (half-precision storage path, whose collision is
+// binary32): the node - centre displacement is formed in binary64 and rounded
+// once, the rigid-body velocities and their count-weighted mean are binary32,
+// beta and (1 - beta)/tau are the binary64 table entries rounded.  Holding no
+// binary64 temporaries keeps that kernel at six wavefronts per SIMD.
+template <class L>
+__device__ __forceinline__ int solid_velocity_f32(const LBArgs &a, int64_t n, int nown, int x, int y,
+                                                  int z, float V[3], float &beta, float &arel) {
+    const int64_t N = a.g.N;
+    const int k = nown < MAX_OWNERS ? nown : MAX_OWNERS;
+    uint32_t r[4];
+#pragma unroll
+    for (int j = 0; j < MAX_OWNERS; j++) r[j] = j < k ? a.slots[(int64_t)j * N + n] : 0xffffffffu;
+    sort4(r[0], r[1], r[2], r[3]);
+    int total = 0;
+#pragma unroll
+    for (int j = 0; j < MAX_OWNERS; j++)
+        if (j < k) total += (int)(r[j] & ((1u << SLOT_COUNT_BITS) - 1u));
+    const int cc = total < a.Smax ? total : a.Smax;
+    beta = (float)a.beta_tab[cc];
+    arel = (float)a.arel_tab[cc];
+    float num[3] = {0.0f, 0.0f, 0.0f};
+    const int P = a.np;
+#pragma unroll
+    for (int j = 0; j < MAX_OWNERS; j++) {
+        if (j < k) {
+            const int p = (int)(r[j] >> SLOT_COUNT_BITS);
+            const int cnt = (int)(r[j] & ((1u << SLOT_COUNT_BITS) - 1u));
+            const float rx = (float)node_disp(a.g, 0, x, a.px[p]);
+            const float ry = (float)node_disp(a.g, 1, y, a.px[P + p]);
+            const float U0 = (float)a.pv[p], U1 = (float)a.pv[P + p];
+            const float U2 = L::D == 3 ? (float)a.pv[2 * P + p] : 0.0f;
+            const float W0 = L::D == 3 ? (float)a.pw[p] : 0.0f, W1 = L::D == 3 ? (float)a.pw[P + p] : 0.0f;
+            const float W2 = (float)a.pw[2 * P + p];
+            float vr[3];
+            if (L::D == 3) {
+                const float rz = (float)node_disp(a.g, 2, z, a.px[2 * P + p]);
+                vr[0] = U0 + (W1 * rz - W2 * ry);
+                vr[1] = U1 + (W2 * rx - W0 * rz);
+                vr[2] = U2 + (W0 * ry - W1 * rx);
+            } else {
+                vr[0] = U0 - W2 * ry;
+                vr[1] = U1 + W2 * rx;
+                vr[2] = 0.0f;
+            }
+            const float c = (float)cnt;
+#pragma unroll
+            for (int d = 0; d < L::D; d++) num[d] = num[d] + c * vr[d];
+        }
+    }
+    const float den = (float)total;
+#pragma unroll
+    for (int d = 0; d < 3; d++) V[d] = d < L::D ? num[d] / den : 0.0f;
+    return total;
+}
+
 // ------------------------------------------------------------- pull gather
 // Element (i, x, y, z) of a state array.
 __device__ __forceinline__ uint64_t row_elem(const Geom &g, int Q, int i, int y, int z) {
@@ -262,17 +318,25 @@ __device__ __forceinline__ void collide_shifted(const LBArgs &a, uint64_t n, int
     };
     const bool wave_fluid = !__any(nown != 0);
     float beta = 0.0f, ar = a.arel0f;
-    double Vd[3] = {0.0, 0.0, 0.0};
+    float V[3] = {0.0f, 0.0f, 0.0f};
     int total = 0;
     if (!wave_fluid && nown != 0) {
         if (nown > MAX_OWNERS) atomicOr(a.flags, FLAG_SLOT_OVERFLOW);
-        double bd, ad;
-        total = solid_velocity<L>(a, (int64_t)n, nown, x, y, z, Vd, bd, ad);
-        beta = (float)bd;
-        ar = (float)ad;
+        if (ST == 2) {
+            // half-precision storage: binary32 V_S (six wavefronts per SIMD
+            // instead of five, measured faster); binary32 storage keeps the
+            // binary64 V_S (measured faster there)
+            total = solid_velocity_f32<L>(a, (int64_t)n, nown, x, y, z, V, beta, ar);
+        } else {
+            double Vd[3], bd, ad;
+            total = solid_velocity<L>(a, (int64_t)n, nown, x, y, z, Vd, bd, ad);
+            for (int d = 0; d < 3; d++) V[d] = (float)Vd[d];
+            beta = (float)bd;
+            ar = (float)ad;
+        }
     }
     float mom[3];
-    shifted_node<L, ST == 2>(gg, wave_fluid, beta, ar, (float)Vd[0], (float)Vd[1], (float)Vd[2], a.cgf, put, mom);
+    shifted_node<L, ST == 2>(gg, wave_fluid, beta, ar, V[0], V[1], V[2], a.cgf, put, mom);
     if (nown != 0) {
         QRec32 r;
         r.q[0] = mom[0];
