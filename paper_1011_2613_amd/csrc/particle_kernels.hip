@@ -46,49 +46,37 @@ __device__ __forceinline__ void bbox(const Particles &P, int p, int D, int lo[3]
 // Number of sub-cell samples of a node inside a particle: offsets
 // (k + 1/2)/S - 1/2 per axis from the node, inside test dx^2 + dy^2 (+ dz^2)
 // <= R^2 evaluated left to right, d0/d1/d2 the node-minus-centre displacement.
-// The squared offsets are separable, so a node needs S^D additions; nodes whose
-// nearest sample is outside or whose farthest sample is inside are decided
-// from per-axis extremes, exactly, because rounded addition is monotone.
+// The squared offsets are separable, so a node needs S^D additions.  (Called
+// only for nodes the distance bounds left undecided, so no shortcut for
+// all-inside or all-outside nodes is taken here.)
 template <int D, int S>
 __device__ __forceinline__ int sample_count(double d0, double d1, double d2, double R2) {
-    double sx[S], sy[S], sz[S];
-    double mnx = 1e300, mxx = -1.0, mny = 1e300, mxy = -1.0, mnz = 1e300, mxz = -1.0;
+    double sx[S], sz[S];
 #pragma unroll
     for (int s = 0; s < S; s++) {
         const double off = ((double)s + 0.5) / (double)S - 0.5;
-        const double ex = d0 + off, ey = d1 + off;
+        const double ex = d0 + off;
         sx[s] = ex * ex;
-        sy[s] = ey * ey;
-        mnx = fmin(mnx, sx[s]); mxx = fmax(mxx, sx[s]);
-        mny = fmin(mny, sy[s]); mxy = fmax(mxy, sy[s]);
-        if (D == 3) {
-            const double ez = d2 + off;
-            sz[s] = ez * ez;
-            mnz = fmin(mnz, sz[s]); mxz = fmax(mxz, sz[s]);
-        } else {
-            sz[s] = 0.0;
-        }
+        const double ez = d2 + off;
+        sz[s] = D == 3 ? ez * ez : 0.0;
     }
     int count = 0;
-    if (D == 2) {
-        if (mnx + mny > R2) return 0;
-        if (mxx + mxy <= R2) return S * S;
+    // one row of samples (fixed y offset) per iteration, kept rolled so
+    // that only that row's partial sums are live
+#pragma unroll 1
+    for (int ky = 0; ky < S; ky++) {
+        const double ey = d1 + (((double)ky + 0.5) / (double)S - 0.5);
+        const double sy = ey * ey;
 #pragma unroll
-        for (int ky = 0; ky < S; ky++)
-#pragma unroll
-            for (int kx = 0; kx < S; kx++) count += (sx[kx] + sy[ky] <= R2) ? 1 : 0;
-    } else {
-        if (mnx + mny + mnz > R2) return 0;
-        if (mxx + mxy + mxz <= R2) return S * S * S;
-        // kz innermost: one partial sum sx + sy live at a time
-#pragma unroll
-        for (int ky = 0; ky < S; ky++)
-#pragma unroll
-            for (int kx = 0; kx < S; kx++) {
-                const double t = sx[kx] + sy[ky];
+        for (int kx = 0; kx < S; kx++) {
+            const double t = sx[kx] + sy;
+            if (D == 2) {
+                count += (t <= R2) ? 1 : 0;
+            } else {
 #pragma unroll
                 for (int kz = 0; kz < S; kz++) count += (t + sz[kz] <= R2) ? 1 : 0;
             }
+        }
     }
     return count;
 }
