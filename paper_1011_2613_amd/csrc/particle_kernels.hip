@@ -357,12 +357,12 @@ __device__ __forceinline__ double shfl_xor_d(double v, int m) {
 // accumulators; each wavefront merges its lanes with butterfly shuffles and
 // the first thread merges the wavefronts in a fixed order.
 // F_p = -sum, T_p = -sum.
-template <int D, bool R32>
-__global__ __launch_bounds__(256) void k_force(ForceArgs a) {
-    __shared__ double part[4][12];
+template <int D, bool R32, int NT>
+__global__ __launch_bounds__(NT) void k_force(ForceArgs a) {
+    constexpr int nw = NT / 64;
+    __shared__ double part[nw][12];
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
-    const int nw = blockDim.x >> 6;
     const int p = blockIdx.x;
     const int P = a.P.np;
     const int len = a.P.list_len[p];
@@ -387,32 +387,38 @@ __global__ __launch_bounds__(256) void k_force(ForceArgs a) {
     // before the first accumulation, and the list entries of the next round
     // are loaded while they are in flight (the first round's beside the list
     // length: loads below the capacity stay inside the particle's list).
-    constexpr int UN = 4;
-    const int stride = UN * (int)blockDim.x;
+    constexpr int UN = 2;  // 80 registers: six wavefronts per SIMD
+    const int stride = UN * NT;
     uint32_t vn[UN];
 #pragma unroll
     for (int u = 0; u < UN; u++) {
-        const int e = u * (int)blockDim.x + (int)threadIdx.x;
+        const int e = u * NT + (int)threadIdx.x;
         vn[u] = e < cap ? list[e] : 0u;
     }
     for (int e0 = 0; e0 < len; e0 += stride) {
         uint32_t v[UN];
 #pragma unroll
         for (int u = 0; u < UN; u++) {
-            const int e = e0 + u * (int)blockDim.x + (int)threadIdx.x;
+            const int e = e0 + u * NT + (int)threadIdx.x;
             v[u] = e < len ? vn[u] : 0u;
         }
+        // lattice coordinates of an entry, formed again where needed (fewer
+        // registers live across the loads)
+        auto coords = [&](uint32_t e, int &ix, int &iy, int &iz) {
+            ix = wrap1(a.g, 0, lo0 + (int)((e >> 10) & 127u));
+            iy = wrap1(a.g, 1, lo1 + (int)((e >> 17) & 127u));
+            iz = D == 3 ? wrap1(a.g, 2, lo2 + (int)((e >> 24) & 127u)) : 0;
+        };
         double q0[UN], q1[UN], q2[UN];
-        int tot[UN], ix[UN], iy[UN], iz[UN];
+        int tot[UN];
 #pragma unroll
         for (int u = 0; u < UN; u++) {
-            ix[u] = wrap1(a.g, 0, lo0 + (int)((v[u] >> 10) & 127u));
-            iy[u] = wrap1(a.g, 1, lo1 + (int)((v[u] >> 17) & 127u));
-            iz[u] = D == 3 ? wrap1(a.g, 2, lo2 + (int)((v[u] >> 24) & 127u)) : 0;
             q0[u] = q1[u] = q2[u] = 0.0;
             tot[u] = 1;
             if (v[u] != 0u) {
-                const int64_t n = (int64_t)ix[u] + (int64_t)a.g.nx * ((int64_t)iy[u] + (int64_t)a.g.ny * iz[u]);
+                int ix, iy, iz;
+                coords(v[u], ix, iy, iz);
+                const int64_t n = (int64_t)ix + (int64_t)a.g.nx * ((int64_t)iy + (int64_t)a.g.ny * iz);
                 double qq[3];
                 read_qrec(a.qr, R32, n, qq, tot[u]);
                 q0[u] = qq[0];
@@ -422,22 +428,24 @@ __global__ __launch_bounds__(256) void k_force(ForceArgs a) {
         }
 #pragma unroll
         for (int u = 0; u < UN; u++) {
-            const int e = e0 + stride + u * (int)blockDim.x + (int)threadIdx.x;
+            const int e = e0 + stride + u * NT + (int)threadIdx.x;
             vn[u] = e < len ? list[e] : 0u;
         }
 #pragma unroll
         for (int u = 0; u < UN; u++) {
             if (v[u] == 0u) continue;
             const int cnt = (int)(v[u] & LIST_COUNT_MASK);
+            int ix, iy, iz;
+            coords(v[u], ix, iy, iz);
             const double sh = (double)cnt / (double)tot[u];
             const double t0 = sh * q0[u], t1 = sh * q1[u];
-            const double rx = ndisp(a.g, 0, ix[u], xp0);
-            const double ry = ndisp(a.g, 1, iy[u], xp1);
+            const double rx = ndisp(a.g, 0, ix, xp0);
+            const double ry = ndisp(a.g, 1, iy, xp1);
             acc_add(F[0], t0);
             acc_add(F[1], t1);
             if (D == 3) {
                 const double t2 = sh * q2[u];
-                const double rz = ndisp(a.g, 2, iz[u], xp2);
+                const double rz = ndisp(a.g, 2, iz, xp2);
                 acc_add(F[2], t2);
                 acc_add(T[0], ry * t2 - rz * t1);
                 acc_add(T[1], rz * t0 - rx * t2);
@@ -707,13 +715,14 @@ hipError_t launch_foot_paint(const FootArgs &a, int D, hipStream_t s) {
 
 hipError_t launch_force(const ForceArgs &a, hipStream_t s) {
     if (a.P.np == 0) return hipSuccess;
+    // one wavefront per particle
     const dim3 g((unsigned)a.P.np), b(64);
     if (a.D == 2) {
-        if (a.rec32) hipLaunchKernelGGL((k_force<2, true>), g, b, 0, s, a);
-        else hipLaunchKernelGGL((k_force<2, false>), g, b, 0, s, a);
+        if (a.rec32) hipLaunchKernelGGL((k_force<2, true, 64>), g, b, 0, s, a);
+        else hipLaunchKernelGGL((k_force<2, false, 64>), g, b, 0, s, a);
     } else {
-        if (a.rec32) hipLaunchKernelGGL((k_force<3, true>), g, b, 0, s, a);
-        else hipLaunchKernelGGL((k_force<3, false>), g, b, 0, s, a);
+        if (a.rec32) hipLaunchKernelGGL((k_force<3, true, 64>), g, b, 0, s, a);
+        else hipLaunchKernelGGL((k_force<3, false, 64>), g, b, 0, s, a);
     }
     return hipGetLastError();
 }
