@@ -115,6 +115,41 @@ def test_ragged_random_state(gpu_lib, dim, shape, wall):
         assert_close(compare(orc, gpu), label="ragged t=%d" % orc.t)
 
 
+def test_large_mixed_particles_many_chunks(gpu_lib):
+    """Mixed radii whose bounding boxes exceed the footprint kernel's chunk
+    of 1024 nodes (3D R = 6.5: 15^3 = 3375 nodes in four chunks, the last
+    ragged; 2D R = 20: 42^2 = 1764 nodes in two), so list positions carry
+    across chunks; moving and rotating, walls in y."""
+    pos = np.array([[12.0, 12.0, 10.0], [34.0, 14.0, 24.0], [14.0, 28.0, 26.0], [36.0, 30.0, 8.0]])
+    rad = np.array([6.5, 6.0, 5.2, 3.0])
+    vel = I.random_velocities(3, 4, 0.01, 61)
+    om = I.random_velocities(3, 4, 2e-3, 62)
+    parts = (pos, vel, om, rad, np.full(4, 4.0), np.zeros(4, np.uint8))
+    box = (48, 40, 36)
+    say("large spheres", box)
+    orc, gpu = make_pair(gpu_lib, 3, box, 0.6, wall_y=True, fluid_force=(2e-6, 0, 1e-6),
+                         particle_accel=(0, -1e-5, 0), samples=4, kn=400.0, restitution=0.8,
+                         particles=parts, max_radius=6.5)
+    for chunk in (1, 25):
+        orc.step(chunk)
+        gpu.step(chunk)
+        assert_close(compare(orc, gpu), label="large spheres t=%d" % orc.t)
+    pos2 = np.array([[30.0, 30.0, 0.0], [75.0, 50.0, 0.0], [70.0, 15.0, 0.0]])
+    rad2 = np.array([20.0, 9.5, 14.0])
+    vel2 = I.random_velocities(2, 3, 0.01, 63)
+    om2 = np.zeros((3, 3)); om2[:, 2] = [1e-3, -2e-3, 5e-4]
+    parts2 = (pos2, vel2, om2, rad2, np.full(3, 3.0), np.zeros(3, np.uint8))
+    box2 = (96, 80)
+    say("large discs", box2)
+    orc, gpu = make_pair(gpu_lib, 2, box2, 0.7, wall_y=True, fluid_force=(1e-6, 0, 0),
+                         particle_accel=(0, -1e-5, 0), samples=5, kn=400.0, restitution=0.8,
+                         particles=parts2, max_radius=20.0)
+    for chunk in (1, 40):
+        orc.step(chunk)
+        gpu.step(chunk)
+        assert_close(compare(orc, gpu), label="large discs t=%d" % orc.t)
+
+
 def hex_pack(box, R, rows, gap=-0.2, y0=None, seed=0, v=0.01):
     """Discs in a hexagonal packing resting on the lower wall, neighbours
     overlapping by -gap, with seeded random velocities."""
