@@ -50,7 +50,7 @@ def run_variant(binding, inputs, w, parts, storage, steps, warmup):
     sim = binding.Simulation(w.dim, w.shape, w.tau, storage=storage, wall_y=w.wall_y,
                              fluid_force=w.fluid_force, particle_accel=w.particle_accel,
                              samples=w.samples, kn=w.kn, restitution=w.restitution,
-                             max_particles=w.count)
+                             max_particles=w.count, max_radius=w.radius)
     sim.set_particles(*parts)
     sim.step(warmup)
     # timed region: HIP events around the lattice kernel only (on the stream
@@ -222,8 +222,9 @@ def main():
         "vs_baseline": None,
         "dtype": DTYPE["fp64"],
         "data": "synthetic (seeded random sphere placement, fluid at rest)",
-        "config": {"workload": "%s: D3Q19 %dx%dx%d, walls y, %d spheres R=%g, tau %g, density ratio %g"
-                   % (w.name, *w.shape, w.count, w.radius, w.tau, w.rho_ratio),
+        "config": {"workload": "%s: D3Q19 %dx%dx%d, %s, %d spheres R=%g, tau %g, density ratio %g"
+                   % (w.name, *w.shape, "walls y" if w.wall_y else "periodic", w.count, w.radius,
+                      round(w.tau, 4), w.rho_ratio),
                    "nodes": w.nodes, "particles": w.count, "storage": "fp64"},
         "roofline": base["roofline"],
         "phase_ms_per_step": base["phase_ms_per_step"],
@@ -239,7 +240,9 @@ def main():
         print("# ensemble: %s" % out["ensemble"], file=sys.stderr, flush=True)
         out["closure"] = closure_bench(binding)
         print("# closure: %s" % out["closure"], file=sys.stderr, flush=True)
-    if not args.no_cpu_baseline:
+    # the oracle times one full step of the workload (C3: about 9 s on one
+    # core); a lattice much larger than that is not timed on the host
+    if not args.no_cpu_baseline and w.nodes <= 10 ** 8:
         out["cpu_baseline"] = cpu_baseline(w, parts)
     print(json.dumps(out), flush=True)
 

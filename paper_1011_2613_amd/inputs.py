@@ -235,6 +235,12 @@ def workload(name):
         fraction 0.1, density ratio 1000, gravity along -y, 8x8 sampling.
     C3  D3Q19 192x756x192, periodic x/z, walls y, tau 0.6, spheres R = 4 at
         solid fraction 0.08, density ratio 1000, gravity along -y, 4^3 sampling.
+    P3  The paper's 3D suspension at full size (simulation section, Table 2
+        3D column): D3Q19 512x2016x512 periodic on every axis, 129,024
+        spheres d = 10 (solid fraction 0.128), nu 0.2462 (tau 1.2386),
+        density ratio 692.3, gravity 4.704e-7 along -y on the particles and
+        the body force 4.04e-5 along +y on the fluid that balances it,
+        k = 17892, e = 0.9, initial particle speed 5e-3, 4^3 sampling.
     """
     if name == "C1":
         return Workload("C1", 2, (256, 256), 0.6, False, 6.0, 16, 10.0, 8, 1.0e3, 0.9, 1000,
@@ -256,5 +262,10 @@ def workload(name):
         n = 16000 if name == "C3dense" else solid_fraction_count(3, shape, 4.0, 0.08)
         return Workload(name, 3, shape, tau, True, 4.0, n, rr, 4,
                         _kn_for_contact_time(3, rr, 4.0, 0.9), 0.9, 2000, seed=3, v0=5.0e-3,
+                        particle_accel=(0.0, -(1.0 - 1.0 / rr) * g, 0.0))
+    if name == "P3":
+        nu, rr, g = 0.2462, 692.3, 4.704e-7
+        return Workload("P3", 3, (512, 2016, 512), 0.5 + 3.0 * nu, False, 5.0, 129024, rr, 4,
+                        17892.0, 0.9, 2000, seed=4, v0=5.0e-3, fluid_force=(0.0, 4.04e-5, 0.0),
                         particle_accel=(0.0, -(1.0 - 1.0 / rr) * g, 0.0))
     raise KeyError(name)

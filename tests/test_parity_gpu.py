@@ -306,3 +306,67 @@ def test_full_size_first_steps(gpu_lib, name, steps):
     # mass is conserved to rounding at full size
     rho, _ = gpu.macro()
     assert abs(rho.sum() - w.nodes) / w.nodes < 1e-13
+
+
+# ------------------------------------- the paper's 3D suspension at full size
+def test_paper_scale_3d_sampled_first_step(gpu_lib):
+    """The paper's 3D suspension at full size (512x2016x512 D3Q19, 129,024
+    spheres, FP64: about 190 GB of device memory on one GPU), one step from
+    the seeded initial state.  The oracle cannot hold this lattice, but one
+    step is local: a particle's force, contact force and new state depend only
+    on the uniform initial fluid and the particles within a few radii.  Each
+    sampled particle is checked against the oracle run on a periodic 48^3
+    sub-box centred on it (holding every particle whose centre lies in it,
+    shifted by whole lattice units); the total mass of the full lattice is
+    checked after three steps."""
+    import torch
+    w = I.workload("P3")
+    parts = w.particles()
+    pos = parts[0]
+    L = np.array(w.shape, dtype=np.float64)
+    say("paper scale", w.shape, w.count, "particles")
+    torch.cuda.empty_cache()
+    gpu = gpu_lib.Simulation(3, w.shape, w.tau, storage="fp64", wall_y=False,
+                             fluid_force=w.fluid_force, particle_accel=w.particle_accel,
+                             samples=w.samples, kn=w.kn, restitution=w.restitution,
+                             max_particles=w.count, max_radius=w.radius)
+    gpu.set_particles(*parts)
+    gpu.step(1)
+    F1, T1 = gpu.forces()
+    Fc1 = gpu.contact_forces()
+    x1, v1, w1 = gpu.particles()
+    from oracle import oracle as O
+    E = 48
+    rng = np.random.default_rng(5)
+    for p in sorted(rng.choice(w.count, 4, replace=False)):
+        c = pos[p]
+        org = np.floor(c) - E // 2
+        # periodic image nearest to c; kept when it lies within E/2 - R - 1 of c
+        # on every axis, so no two kept particles meet across the sub-box seam
+        img = pos - L * np.round((pos - c) / L)
+        sel = np.flatnonzero(np.all(np.abs(img - c) < E // 2 - w.radius - 1, axis=1))
+        sub = img[sel] - org               # exact for particles that needed no wrap
+        k = int(np.flatnonzero(sel == p)[0])
+        orc = O.OracleSim(3, (E, E, E), w.tau, wall_y=False, fluid_force=w.fluid_force,
+                          particle_accel=w.particle_accel, samples=w.samples, kn=w.kn,
+                          restitution=w.restitution)
+        orc.set_particles(sub, parts[1][sel], parts[2][sel], parts[3][sel], parts[4][sel], parts[5][sel])
+        orc.step(1)
+        F0, T0 = orc.forces()
+        x0, v0, w0 = orc.particles()
+        xg = x1[p] - org
+        xg -= L * np.round((xg - x0[k]) / L)
+        errs = {"F": rel_err(F1[p], F0[k]), "T": rel_err(T1[p], T0[k]),
+                "Fc": rel_err(Fc1[p], orc.contact_forces()[k]), "v": rel_err(v1[p], v0[k]),
+                "w": rel_err(w1[p], w0[k]), "x": rel_err(xg, x0[k])}
+        orc.close()
+        assert_close(errs, label="paper scale particle %d (%d in sub-box)" % (p, len(sel)))
+    gpu.step(2)
+    rho, u = gpu.macro_device()
+    mass = float(rho.sum())
+    del rho, u
+    gpu.close()
+    del gpu
+    torch.cuda.empty_cache()
+    say("paper scale mass error %.2e" % (abs(mass - w.nodes) / w.nodes))
+    assert abs(mass - w.nodes) / w.nodes < 1e-13
