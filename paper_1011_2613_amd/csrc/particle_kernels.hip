@@ -154,10 +154,10 @@ __device__ __forceinline__ int classify(double d0, double d1, double d2, double 
 // Footprint of one particle, one workgroup.  The bounding box is taken in
 // chunks of nodes: (A) every node is classified by distance bounds, undecided
 // nodes are queued in LDS; (B) the queued nodes get the exact per-sample count,
-// the workgroup's lanes all busy with such nodes; (C) in node order (x
-// fastest), a workgroup prefix sum over covered nodes gives each its place in
-// the particle's list, and the thread claims an owner slot and writes the
-// entry, so the list is the same on every run.
+// the workgroup's lanes all busy with such nodes; (C1) a workgroup prefix sum
+// lists the covered nodes of the chunk in node order (x fastest); (C2) the
+// k-th covered node takes place k of the particle's list and an owner slot, so
+// the list is the same on every run.
 template <int D, int S, int NT>
 __global__ __launch_bounds__(NT) void k_foot_paint(FootArgs a) {
     constexpr int CHUNK = 1024;
