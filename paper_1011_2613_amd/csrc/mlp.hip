@@ -7,10 +7,11 @@
 //   B (32 x 16): lane l holds B[8 (l / 16) + j][l % 16]
 //   D (16 x 16): lane l holds D[4 (l / 16) + i][l % 16], i = 0..3
 //
-// Forward: one workgroup of four wavefronts keeps all weights in LDS as
+// Forward: one workgroup of twelve wavefronts keeps all weights in LDS as
 // bfloat16 (rows padded so the 16 rows a fragment touches fall in distinct LDS
-// banks) and loops over 16-row tiles, one tile per wavefront; activations stay
-// in LDS between layers.  Training mode also writes pre-activations and the
+// banks) and loops over 16-row tiles, one tile per wavefront; a layer's eight
+// output tiles accumulate in registers (eight independent MFMA chains per A
+// fragment) and then overwrite the wavefront's activation tile in LDS.  Training mode also writes pre-activations and the
 // bfloat16 activations to HBM for the backward pass.
 // Backward: weight gradients dW = dZ^T H and input gradients dH = dZ W are
 // MFMA GEMMs where one wavefront owns one 16 x 16 output tile and runs over the
@@ -72,26 +73,39 @@ struct FwdArgs {
     float *z1, *z2, *z3;
 };
 
-// One dense layer for a 16-row tile held in LDS (row stride SIN): out = in W^T.
-template <int K, int SIN, int SW>
-__device__ __forceinline__ void layer_tile(const __bf16 *sin, const __bf16 *sw, int nt, f32x4 &acc) {
+// One dense layer for a 16-row tile held in LDS (row stride SIN): the NT
+// output tiles of 16 columns, acc[nt] = in W[16 nt .. 16 nt + 15]^T.  The
+// reduction index is outermost, so one A fragment feeds NT independent MFMA
+// chains; each output element still accumulates its K/32 products in
+// ascending order.
+template <int K, int SIN, int SW, int NT>
+__device__ __forceinline__ void layer_tiles(const __bf16 *sin, const __bf16 *sw, f32x4 (&acc)[NT]) {
     const int l = threadIdx.x & 63;
-    acc = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+    for (int nt = 0; nt < NT; nt++) acc[nt] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
     for (int kt = 0; kt < K / 32; kt++) {
         const bf16x8 a = *(const bf16x8 *)(sin + (l & 15) * SIN + kt * 32 + 8 * (l >> 4));
-        const bf16x8 b = *(const bf16x8 *)(sw + (nt * 16 + (l & 15)) * SW + kt * 32 + 8 * (l >> 4));
-        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc, 0, 0, 0);
+#pragma unroll
+        for (int nt = 0; nt < NT; nt++) {
+            const bf16x8 b = *(const bf16x8 *)(sw + (nt * 16 + (l & 15)) * SW + kt * 32 + 8 * (l >> 4));
+            acc[nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[nt], 0, 0, 0);
+        }
     }
 }
 
+// Forward workgroup: FWD_WAVES wavefronts share the bfloat16 weights in LDS;
+// each wavefront owns one activation tile (16 rows) that every layer
+// overwrites in place once its products are in registers.
+constexpr int FWD_WAVES = 12;
+
 template <bool TRAIN>
-__global__ __launch_bounds__(256) void k_mlp_forward(FwdArgs a) {
+__global__ __launch_bounds__(64 * FWD_WAVES) void k_mlp_forward(FwdArgs a) {
     __shared__ __attribute__((aligned(16))) __bf16 sW1[NH * S1];
     __shared__ __attribute__((aligned(16))) __bf16 sW2[NH * SH];
     __shared__ __attribute__((aligned(16))) __bf16 sW3[NH * SH];
     __shared__ __attribute__((aligned(16))) __bf16 sW4[16 * SH];
-    __shared__ __attribute__((aligned(16))) __bf16 sAct[4][2][16 * SH];
+    __shared__ __attribute__((aligned(16))) __bf16 sAct[FWD_WAVES][16 * SH];
     const int tid = threadIdx.x, l = tid & 63, wv = tid >> 6;
     // weights -> LDS, 8 bf16 per copy
     for (int c = tid; c < NH * KIN / 8; c += blockDim.x) {
@@ -108,9 +122,10 @@ __global__ __launch_bounds__(256) void k_mlp_forward(FwdArgs a) {
         *(bf16x8 *)(sW4 + r * SH + k) = *(const bf16x8 *)(a.w.w4 + r * NH + k);
     }
     __syncthreads();
-    __bf16 *bufA = sAct[wv][0], *bufB = sAct[wv][1];
+    __bf16 *buf = sAct[wv];
     const int64_t ntiles = (a.n + 15) / 16;
-    for (int64_t tile = (int64_t)blockIdx.x * 4 + wv; tile < ntiles; tile += (int64_t)gridDim.x * 4) {
+    for (int64_t tile = (int64_t)blockIdx.x * FWD_WAVES + wv; tile < ntiles;
+         tile += (int64_t)gridDim.x * FWD_WAVES) {
         const int64_t r0 = tile * 16;
         // input tile: 16 rows x 64 (40 features, zero padded), binary32 -> bfloat16
         for (int c = l; c < 16 * KIN; c += 64) {
@@ -118,30 +133,30 @@ __global__ __launch_bounds__(256) void k_mlp_forward(FwdArgs a) {
             const int64_t row = r0 + r;
             const float v = (k < NIN && row < a.n) ? a.X[row * NIN + k] : 0.0f;
             const __bf16 q = (__bf16)v;
-            bufA[r * S1 + k] = q;
+            buf[r * S1 + k] = q;
             if (TRAIN && row < a.n) a.h0[row * KIN + k] = q;
         }
         wave_sync();
         // hidden layers
 #pragma unroll
         for (int layer = 0; layer < 3; layer++) {
-            const __bf16 *in = layer == 1 ? bufB : bufA;
-            __bf16 *out = layer == 1 ? bufA : bufB;
             const float *bias = a.p + (layer == 0 ? OFF_B1 : (layer == 1 ? OFF_B2 : OFF_B3));
             __bf16 *hg = layer == 0 ? a.h1 : (layer == 1 ? a.h2 : a.h3);
             float *zg = layer == 0 ? a.z1 : (layer == 1 ? a.z2 : a.z3);
+            f32x4 acc[NH / 16];
+            if (layer == 0) layer_tiles<KIN, S1, S1, NH / 16>(buf, sW1, acc);
+            else layer_tiles<NH, SH, SH, NH / 16>(buf, layer == 1 ? sW2 : sW3, acc);
+            wave_sync();  // every lane's reads of the input tile are done
+#pragma unroll
             for (int nt = 0; nt < NH / 16; nt++) {
-                f32x4 acc;
-                if (layer == 0) layer_tile<KIN, S1, S1>(in, sW1, nt, acc);
-                else layer_tile<NH, SH, SH>(in, layer == 1 ? sW2 : sW3, nt, acc);
                 const int col = nt * 16 + (l & 15);
                 const float b = bias[col];
 #pragma unroll
                 for (int i = 0; i < 4; i++) {
                     const int r = 4 * (l >> 4) + i;
-                    const float z = acc[i] + b;
+                    const float z = acc[nt][i] + b;
                     const __bf16 h = (__bf16)silu(z);
-                    out[r * SH + col] = h;
+                    buf[r * SH + col] = h;
                     if (TRAIN && r0 + r < a.n) {
                         zg[(r0 + r) * NH + col] = z;
                         hg[(r0 + r) * NH + col] = h;
@@ -151,14 +166,14 @@ __global__ __launch_bounds__(256) void k_mlp_forward(FwdArgs a) {
             wave_sync();
         }
         // output layer: W4 padded to 16 rows, column 0 of the result is y
-        f32x4 acc;
-        layer_tile<NH, SH, SH>(bufB, sW4, 0, acc);
+        f32x4 acc[1];
+        layer_tiles<NH, SH, SH, 1>(buf, sW4, acc);
         if ((l & 15) == 0) {
             const float b4 = a.p[OFF_B4];
 #pragma unroll
             for (int i = 0; i < 4; i++) {
                 const int64_t row = r0 + 4 * (l >> 4) + i;
-                if (row < a.n) a.y[row] = acc[i] + b4;
+                if (row < a.n) a.y[row] = acc[0][i] + b4;
             }
         }
         wave_sync();
@@ -377,8 +392,8 @@ hipError_t grads(mlp_ctx *c, const float *X, const float *y, int64_t n) {
     fa.h3 = P<__bf16>(c, L.h3);
     fa.z1 = P<float>(c, L.z1); fa.z2 = P<float>(c, L.z2); fa.z3 = P<float>(c, L.z3);
     const int64_t tiles = (n + 15) / 16;
-    const unsigned blocks = (unsigned)std::min<int64_t>((tiles + 3) / 4, 1024);
-    hipLaunchKernelGGL(k_mlp_forward<true>, dim3(blocks), dim3(256), 0, c->s, fa);
+    const unsigned blocks = (unsigned)std::min<int64_t>((tiles + FWD_WAVES - 1) / FWD_WAVES, 1024);
+    hipLaunchKernelGGL(k_mlp_forward<true>, dim3(blocks), dim3(64 * FWD_WAVES), 0, c->s, fa);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     float *g = P<float>(c, L.g);
     hipLaunchKernelGGL(k_out_grad, dim3((unsigned)((npad + 255) / 256)), dim3(256), 0, c->s,
@@ -483,8 +498,8 @@ int mlp_forward(mlp_ctx *c, const float *X, int64_t n, float *y) {
     FwdArgs fa{};
     fa.X = X; fa.n = n; fa.p = P<float>(c, c->L.p); fa.w = c->w; fa.y = y;
     const int64_t tiles = (n + 15) / 16;
-    const unsigned blocks = (unsigned)std::min<int64_t>((tiles + 3) / 4, 1024);
-    hipLaunchKernelGGL(k_mlp_forward<false>, dim3(blocks), dim3(256), 0, c->s, fa);
+    const unsigned blocks = (unsigned)std::min<int64_t>((tiles + FWD_WAVES - 1) / FWD_WAVES, 1024);
+    hipLaunchKernelGGL(k_mlp_forward<false>, dim3(blocks), dim3(64 * FWD_WAVES), 0, c->s, fa);
     return hipGetLastError() == hipSuccess ? LBM_OK : LBM_E_HIP;
 }
 
