@@ -285,11 +285,6 @@ hipError_t enqueue_step(lbm_ctx *c, int from, hipStream_t s, int slot) {
         phase_begin(c, 0, s);
         if ((e = launch_foot_paint(fa, c->L.D, s)) != hipSuccess) return e;
         phase_end(c, s);
-        // contact forces are needed by the force kernel (integration); the
-        // join sits before the lattice kernel, by when the cell list and the
-        // contacts (shorter than the footprint) are done, so no wait sits
-        // between the lattice and force kernels
-        if ((e = hipStreamWaitEvent(s, c->ev_join[slot], 0)) != hipSuccess) return e;
     }
     phase_begin(c, 1, s);
     if ((e = launch_lb(lattice, storage, lb_args(c, from), s)) != hipSuccess) return e;
@@ -303,6 +298,9 @@ hipError_t enqueue_step(lbm_ctx *c, int from, hipStream_t s, int slot) {
         fo.D = c->L.D;
         fo.integrate = 1;
         for (int d = 0; d < 3; d++) fo.ap[d] = c->cfg.particle_accel[d];
+        // the force kernel integrates: it needs the contact forces; the cell
+        // list and the contacts overlap the footprint and lattice kernels
+        if ((e = hipStreamWaitEvent(s, c->ev_join[slot], 0)) != hipSuccess) return e;
         phase_begin(c, 2, s);
         if ((e = launch_force(fo, s)) != hipSuccess) return e;
         phase_end(c, s);
