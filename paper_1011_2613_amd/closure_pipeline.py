@@ -88,8 +88,8 @@ def main(argv=None):
 
     test_boxes = E.sample_boxes(args.heldout, 9000)
     say("held-out: %d boxes" % len(test_boxes))
-    Xte, yte, _, test_stats = run_ensemble(test_boxes, max_steps=args.max_steps, check_every=args.check_every,
-                                           tol=args.tol, tune_cache=args.tune_cache)
+    Xte, yte, bte, test_stats = run_ensemble(test_boxes, max_steps=args.max_steps, check_every=args.check_every,
+                                             tol=args.tol, tune_cache=args.tune_cache)
     say("  steady %d/%d boxes, %d samples" % (test_stats["steady_boxes"], test_stats["boxes"], test_stats["samples"]))
 
     ok = np.isfinite(ytr) & (ytr > 0)
@@ -100,7 +100,8 @@ def main(argv=None):
     train_s = time.perf_counter() - t0
     steps_per_epoch = max(1, math.ceil(len(ytr) / args.batch))
 
-    res = E.evaluate(mlp, norm, Xte, yte)
+    okte = np.isfinite(yte) & (yte > 0)
+    res = E.evaluate(mlp, norm, Xte[okte], yte[okte], box_of=bte[okte])
     res_train = E.evaluate(mlp, norm, Xtr[: min(len(ytr), 20000)], ytr[: min(len(ytr), 20000)])
 
     # inference throughput on rows drawn from the training distribution,

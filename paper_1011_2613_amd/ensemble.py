@@ -275,11 +275,14 @@ def predict(mlp, norm, X):
     return np.exp(y)
 
 
-def evaluate(mlp, norm, X, y):
+def evaluate(mlp, norm, X, y, box_of=None):
     """Closure vs resolved drag on held-out particles.  Particles outside the
     training envelope fall back to the resolved drag (zero error, counted).
     The Wen-Yu-type correlation (no learning) uses the local solid fraction
-    (feature 0, with the box value as floor) and the box Reynolds number."""
+    (feature 0, with the box value as floor) and the box Reynolds number.
+    With `box_of` (the box of each particle) the errors of the box means
+    (mean predicted drag of a box's particles against their mean resolved
+    drag) are reported as well."""
     PHI_BOX, LOG_RE = NFEAT - 3, 1
     inside = norm.inside(X)
     pred = predict(mlp, norm, X)
@@ -291,8 +294,20 @@ def evaluate(mlp, norm, X, y):
     t0 = time.perf_counter()
     _ = predict(mlp, norm, X)
     t1 = time.perf_counter()
-    return {"n": int(len(y)), "fallback_fraction": float(1.0 - inside.mean()),
-            "mlp_mean_rel_err": float(err_used.mean()), "mlp_mean_rel_err_inside": float(err_mlp[inside].mean())
-            if inside.any() else float("nan"),
-            "mlp_median_rel_err": float(np.median(err_used)),
-            "wen_yu_mean_rel_err": float(err_wy.mean()), "inference_s": t1 - t0}
+    out = {"n": int(len(y)), "fallback_fraction": float(1.0 - inside.mean()),
+           "mlp_mean_rel_err": float(err_used.mean()), "mlp_mean_rel_err_inside": float(err_mlp[inside].mean())
+           if inside.any() else float("nan"),
+           "mlp_median_rel_err": float(np.median(err_used)),
+           "wen_yu_mean_rel_err": float(err_wy.mean()), "inference_s": t1 - t0}
+    if box_of is not None:
+        used = np.where(inside, pred, y)
+        eb_mlp, eb_wy = [], []
+        for b in np.unique(box_of):
+            m = box_of == b
+            ref = y[m].mean()
+            eb_mlp.append(abs(used[m].mean() - ref) / abs(ref))
+            eb_wy.append(abs(wy[m].mean() - ref) / abs(ref))
+        out.update({"boxes": len(eb_mlp), "mlp_box_mean_rel_err": float(np.mean(eb_mlp)),
+                    "mlp_box_max_rel_err": float(np.max(eb_mlp)),
+                    "wen_yu_box_mean_rel_err": float(np.mean(eb_wy))})
+    return out
