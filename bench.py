@@ -45,12 +45,12 @@ def measured_traffic(storage, workload):
     return rec.get("bytes_per_launch")
 
 
-def run_variant(binding, inputs, w, parts, storage, steps, warmup):
+def run_variant(binding, inputs, w, parts, storage, steps, warmup, eps="sampling"):
     import torch
     sim = binding.Simulation(w.dim, w.shape, w.tau, storage=storage, wall_y=w.wall_y,
                              fluid_force=w.fluid_force, particle_accel=w.particle_accel,
                              samples=w.samples, kn=w.kn, restitution=w.restitution,
-                             max_particles=w.count, max_radius=w.radius)
+                             max_particles=w.count, max_radius=w.radius, eps=eps)
     sim.set_particles(*parts)
     sim.step(warmup)
     # timed region: HIP events around the lattice kernel only (on the stream
@@ -180,6 +180,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=30)
     ap.add_argument("--workload", default="C3")
     ap.add_argument("--variants", default="fp64,fp32s,fp16s")
+    ap.add_argument("--eps", default="sampling", choices=["sampling", "table"],
+                    help="solid fraction by sub-cell sampling or by the paper's table lookup")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the batched-ensemble and closure measurements")
@@ -204,7 +206,7 @@ def main():
         variants = ["fp64"] + variants
     res = {}
     for v in variants:
-        res[v] = run_variant(binding, inputs, w, parts, v, args.steps, args.warmup)
+        res[v] = run_variant(binding, inputs, w, parts, v, args.steps, args.warmup, eps=args.eps)
         print("# %s: %.1f MLUPS, lattice kernel %.3f ms, %.1f GB/s"
               % (v, res[v]["mlups"], res[v]["lattice_kernel_ms"], res[v]["roofline"]["achieved"]),
               file=sys.stderr, flush=True)
@@ -225,7 +227,7 @@ def main():
         "config": {"workload": "%s: D3Q19 %dx%dx%d, %s, %d spheres R=%g, tau %g, density ratio %g"
                    % (w.name, *w.shape, "walls y" if w.wall_y else "periodic", w.count, w.radius,
                       round(w.tau, 4), w.rho_ratio),
-                   "nodes": w.nodes, "particles": w.count, "storage": "fp64"},
+                   "nodes": w.nodes, "particles": w.count, "storage": "fp64", "eps": args.eps},
         "roofline": base["roofline"],
         "phase_ms_per_step": base["phase_ms_per_step"],
         "variants": {v: {"value": round(r["mlups"], 1), "unit": "MLUPS", "dtype": DTYPE[v],

@@ -58,6 +58,18 @@ enum { LBM_FP64 = 0, LBM_FP32_SHIFTED = 1, LBM_FP16_STORE = 2 };
 
 enum { LBM_HOST = 0, LBM_DEVICE = 1 };
 
+/* Solid fraction eps of a node's cell ("Numerical scheme", Fig. 1).
+ * SAMPLING: the count of S^D sub-cell sample points inside the particle.
+ * TABLE: the paper's table lookup, eps = phi(d, theta) (Eq. 6): for the one
+ * particle radius in use, a table of counts on the same S^D scale indexed by
+ * rho = |r| - R (64 bins over [-sqrt(D)/2, sqrt(D)/2]) and by the direction
+ * of r folded into the symmetric wedge (sorted component magnitudes
+ * a >= b >= c; t1 = b/|r| and, in 3D, t2 = c/|r|, 16 bins each over
+ * [0, 1/sqrt(2)] and [0, 1/sqrt(3)]); an entry is the coverage of the cell
+ * centred at its bin centre measured with 16^D reference points, rounded to
+ * the S^D scale.  Requires every particle to have the same radius R >= 1. */
+enum { LBM_EPS_SAMPLING = 0, LBM_EPS_TABLE = 1 };
+
 #define LBM_MAX_OWNERS 4      /* particles that may cover one node */
 #define LBM_MAX_CONTACTS 32   /* contacts per particle per step */
 #define LBM_MAX_PARTICLES 4194303
@@ -80,6 +92,7 @@ typedef struct lbm_config {
     int max_particles;      /* capacity reserved in the workspace */
     double max_radius;      /* largest particle radius the workspace is sized for
                                (<= 0 selects 8 lattice units) */
+    int eps_mode;           /* LBM_EPS_SAMPLING or LBM_EPS_TABLE */
 } lbm_config;
 
 typedef struct lbm_ctx lbm_ctx;

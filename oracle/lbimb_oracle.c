@@ -21,6 +21,12 @@
  *   - body force: F_i = 3 w_i rho (c_i . g), u excludes any half-force shift;
  *   - eps by sub-cell sampling, S points per axis at offsets (k+1/2)/S - 1/2,
  *     inside test dx^2+dy^2(+dz^2) <= R^2, eps = min(count, S^D) / S^D;
+ *   - eps by table lookup (Eq. 6, gamma = phi(d, theta)), the alternative the
+ *     paper ran on its GPUs: for one particle radius a table holds the count
+ *     on the S^D scale as a function of rho = |r| - R (r the node-minus-centre
+ *     displacement) and of the direction of r folded into the symmetric wedge
+ *     (sorted magnitudes a >= b >= c of its components, t1 = b/|r|,
+ *     t2 = c/|r|); see eps_table_build for the bins and the reference counts;
  *   - several particles on a node: one eps from the summed count, V_S the
  *     count-weighted mean of the owners' rigid-body velocities (ascending
  *     particle id), force shares count_pn / count_n;
@@ -97,6 +103,9 @@ typedef struct orc_sim {
     double gf[3];        /* fluid body force per unit mass */
     double ap[3];        /* particle acceleration (gravity incl. buoyancy) */
     int S;               /* sub-samples per axis for eps */
+    int eps_mode;        /* 0: sub-cell sampling, 1: table lookup (Eq. 6) */
+    int *tab;            /* lookup table (eps_mode 1), for radius tab_R */
+    double tab_R;
     double kn, restitution, ce; /* ce = -2 ln e / sqrt(pi^2 + ln^2 e) */
     int couple;          /* 0: hydrodynamic force on particles switched off */
 
@@ -224,6 +233,97 @@ static int sample_count(const orc_sim *s, int p, int ix, int iy, int iz) {
     return count;
 }
 
+/* ------------------------------------------------ eps by table lookup (Eq. 6)
+ * A node's cell is the unit square/cube centred on it.  With H = sqrt(D)/2
+ * (half its diagonal), the cell is wholly inside the particle when
+ * rho = |r| - R <= -H and wholly outside when rho >= H.  In between,
+ * rho falls in one of TAB_NRHO bins of width 2H/TAB_NRHO, t1 = b/|r| in
+ * [0, 1/sqrt(2)] in one of TAB_NT bins (index floor(t1 * sqrt(2) * TAB_NT)),
+ * and in 3D t2 = c/|r| in [0, 1/sqrt(3)] likewise (floor(t2 * sqrt(3) * TAB_NT)).
+ * The entry of a bin is the coverage of the cell whose centre sits at the bin
+ * centre (|r| = R + rho_c, components (a, b, c) = (sqrt(|r|^2 - b^2 - c^2),
+ * t1_c |r|, t2_c |r|)), measured with TAB_M^D reference points at offsets
+ * (k+1/2)/TAB_M - 1/2 and the inside test of the sampling rule, and put on
+ * the S^D scale by integer rounding: (k_in S^D + TAB_M^D/2) / TAB_M^D. */
+#define TAB_NRHO 64
+#define TAB_NT 16
+#define TAB_M 16
+
+static int eps_table_len(int D) { return TAB_NRHO * TAB_NT * (D == 3 ? TAB_NT : 1); }
+
+static void eps_table_build(int D, int S, double R, int *tab) {
+    const double H = sqrt((double)D) * 0.5;
+    const double wr = 2.0 * H / (double)TAB_NRHO;
+    const double k1 = sqrt(2.0) * (double)TAB_NT, k2 = sqrt(3.0) * (double)TAB_NT;
+    const long Smax = D == 3 ? (long)S * S * S : (long)S * S;
+    const long Mtot = D == 3 ? (long)TAB_M * TAB_M * TAB_M : (long)TAB_M * TAB_M;
+    const double R2 = R * R;
+    const int n2 = D == 3 ? TAB_NT : 1;
+    for (int ir = 0; ir < TAB_NRHO; ir++)
+        for (int i1 = 0; i1 < TAB_NT; i1++)
+            for (int i2 = 0; i2 < n2; i2++) {
+                double rn = R + (-H + ((double)ir + 0.5) * wr);
+                double b = ((double)i1 + 0.5) / k1 * rn;
+                double c = D == 3 ? ((double)i2 + 0.5) / k2 * rn : 0.0;
+                double a2 = rn * rn - b * b - c * c;
+                double a = a2 > 0.0 ? sqrt(a2) : 0.0;
+                long kin = 0;
+                int mz = D == 3 ? TAB_M : 1;
+                for (int kz = 0; kz < mz; kz++)
+                    for (int ky = 0; ky < TAB_M; ky++)
+                        for (int kx = 0; kx < TAB_M; kx++) {
+                            double dx = a + (((double)kx + 0.5) / (double)TAB_M - 0.5);
+                            double dy = b + (((double)ky + 0.5) / (double)TAB_M - 0.5);
+                            double r2 = dx * dx + dy * dy;
+                            if (D == 3) {
+                                double dz = c + (((double)kz + 0.5) / (double)TAB_M - 0.5);
+                                r2 = r2 + dz * dz;
+                            }
+                            if (r2 <= R2) kin++;
+                        }
+                tab[(ir * TAB_NT + i1) * n2 + i2] = (int)((kin * Smax + Mtot / 2) / Mtot);
+            }
+}
+
+/* Count on the S^D scale of a node at displacement (d0, d1, d2) from the
+ * centre of a particle of radius R (the table's radius). */
+static int eps_table_lookup(int D, int S, double R, const int *tab, double d0, double d1, double d2) {
+    const double H = sqrt((double)D) * 0.5;
+    const double wr = 2.0 * H / (double)TAB_NRHO;
+    const double k1 = sqrt(2.0) * (double)TAB_NT, k2 = sqrt(3.0) * (double)TAB_NT;
+    const int Smax = D == 3 ? S * S * S : S * S;
+    double r2 = d0 * d0 + d1 * d1;
+    if (D == 3) r2 = r2 + d2 * d2;
+    double r = sqrt(r2);
+    double rho = r - R;
+    if (rho <= -H) return Smax;
+    if (rho >= H) return 0;
+    int ir = (int)floor((rho + H) / wr);
+    if (ir < 0) ir = 0;
+    if (ir > TAB_NRHO - 1) ir = TAB_NRHO - 1;
+    /* sorted magnitudes a >= b >= c */
+    double a = fabs(d0), b = fabs(d1), c = D == 3 ? fabs(d2) : 0.0, t;
+    if (b > a) { t = a; a = b; b = t; }
+    if (c > b) { t = b; b = c; c = t; }
+    if (b > a) { t = a; a = b; b = t; }
+    (void)a;
+    int i1 = (int)floor(b / r * k1);
+    if (i1 > TAB_NT - 1) i1 = TAB_NT - 1;
+    if (D == 2) return tab[ir * TAB_NT + i1];
+    int i2 = (int)floor(c / r * k2);
+    if (i2 > TAB_NT - 1) i2 = TAB_NT - 1;
+    return tab[(ir * TAB_NT + i1) * TAB_NT + i2];
+}
+
+/* Count of particle p on node (ix,iy,iz) in the selected eps mode. */
+static int node_count(const orc_sim *s, int p, int ix, int iy, int iz) {
+    if (s->eps_mode == 0) return sample_count(s, p, ix, iy, iz);
+    double d0 = node_disp(s, 0, ix, s->x[3 * p + 0]);
+    double d1 = node_disp(s, 1, iy, s->x[3 * p + 1]);
+    double d2 = s->L.D == 3 ? node_disp(s, 2, iz, s->x[3 * p + 2]) : 0.0;
+    return eps_table_lookup(s->L.D, s->S, s->R[p], s->tab, d0, d1, d2);
+}
+
 /* ------------------------------------------------------------- lifecycle */
 orc_sim *orc_create(int dim, int nx, int ny, int nz, int wall_y, double tau,
                     const double *gf, const double *ap, int samples,
@@ -275,7 +375,7 @@ static void free_particles(orc_sim *s) {
 void orc_destroy(orc_sim *s) {
     if (!s) return;
     free_particles(s);
-    free(s->f); free(s->fs); free(s->ctot); free(s->vnum); free(s->q);
+    free(s->f); free(s->fs); free(s->ctot); free(s->vnum); free(s->q); free(s->tab);
     free(s);
 }
 
@@ -286,6 +386,8 @@ static int nx_of(const orc_sim *s) { return s->nx; }
 /* Particle arrays are [np][3]; 2D ignores z and uses omega[.][2] only.
  * Mass: rho_s pi R^2 (disc of unit depth) or rho_s (4/3) pi R^3;
  * moment of inertia: m R^2 / 2 (disc) or 2 m R^2 / 5 (sphere). */
+int orc_set_eps_mode(orc_sim *s, int mode);
+
 int orc_set_particles(orc_sim *s, int np, const double *pos, const double *vel,
                       const double *omega, const double *radius,
                       const double *rho_s, const unsigned char *fixed) {
@@ -334,6 +436,8 @@ int orc_set_particles(orc_sim *s, int np, const double *pos, const double *vel,
         }
         s->fixed[p] = fixed ? fixed[p] : 0;
     }
+    /* a lookup table belongs to the radius of the particles it was built for */
+    if (s->eps_mode == 1 && orc_set_eps_mode(s, 1) != 0) return -1;
     return 0;
 }
 
@@ -407,7 +511,7 @@ static void footprint(orc_sim *s) {
                     int ix = wrap_coord(s, 0, cx), iy = wrap_coord(s, 1, cy);
                     int iz = D == 3 ? wrap_coord(s, 2, cz) : 0;
                     if (ix < 0 || iy < 0 || iz < 0) continue;
-                    int cnt = sample_count(s, p, ix, iy, iz);
+                    int cnt = node_count(s, p, ix, iy, iz);
                     if (cnt == 0) continue;
                     long n = node_index(s, ix, iy, iz);
                     double rx = node_disp(s, 0, ix, xp[0]);
@@ -542,7 +646,7 @@ static void hydro_forces(orc_sim *s) {
                     int ix = wrap_coord(s, 0, cx), iy = wrap_coord(s, 1, cy);
                     int iz = D == 3 ? wrap_coord(s, 2, cz) : 0;
                     if (ix < 0 || iy < 0 || iz < 0) continue;
-                    int cnt = sample_count(s, p, ix, iy, iz);
+                    int cnt = node_count(s, p, ix, iy, iz);
                     if (cnt == 0) continue;
                     long n = node_index(s, ix, iy, iz);
                     double sh = (double)cnt / (double)s->ctot[n];
@@ -684,7 +788,45 @@ int orc_footprint_counts(orc_sim *s, int *ctot) {
 }
 
 int orc_particle_node_count(const orc_sim *s, int p, int ix, int iy, int iz) {
-    return sample_count(s, p, ix, iy, iz);
+    return node_count(s, p, ix, iy, iz);
+}
+
+/* Selects the eps rule: 0 sub-cell sampling, 1 table lookup.  The table
+ * needs every particle to have the same radius, at least 1 (so that a node
+ * at the centre is wholly inside); returns -1 otherwise.  Call after
+ * orc_set_particles (and again after every later orc_set_particles). */
+int orc_set_eps_mode(orc_sim *s, int mode) {
+    if (mode != 0 && mode != 1) return -1;
+    free(s->tab);
+    s->tab = NULL;
+    s->eps_mode = mode;
+    if (mode == 0) return 0;
+    if (s->np < 1) return -1;
+    double R = s->R[0];
+    for (int p = 1; p < s->np; p++)
+        if (s->R[p] != R) return -1;
+    if (!(R >= 1.0)) return -1;
+    s->tab = (int *)malloc(sizeof(int) * (size_t)eps_table_len(s->L.D));
+    if (!s->tab) return -1;
+    eps_table_build(s->L.D, s->S, R, s->tab);
+    s->tab_R = R;
+    return 0;
+}
+
+/* For tests: the table count of a displacement (d0, d1, d2) for radius R and
+ * S samples per axis (the table of the last (D, S, R) asked for is kept). */
+int orc_eps_table_count(int D, int S, double R, double d0, double d1, double d2) {
+    static int *tab = NULL;
+    static int tD = 0, tS = 0;
+    static double tR = 0.0;
+    if (!tab || tD != D || tS != S || tR != R) {
+        free(tab);
+        tab = (int *)malloc(sizeof(int) * (size_t)eps_table_len(D));
+        if (!tab) return -1;
+        eps_table_build(D, S, R, tab);
+        tD = D; tS = S; tR = R;
+    }
+    return eps_table_lookup(D, S, R, tab, d0, d1, d2);
 }
 
 double orc_sum2(const double *p, long n) {

@@ -51,6 +51,10 @@ def lib():
         L.orc_sum2.restype = C.c_double
         L.orc_beta.argtypes = [C.c_double, C.c_double]
         L.orc_beta.restype = C.c_double
+        L.orc_set_eps_mode.argtypes = [C.c_void_p, C.c_int]
+        L.orc_set_eps_mode.restype = C.c_int
+        L.orc_eps_table_count.argtypes = [C.c_int, C.c_int, C.c_double, C.c_double, C.c_double, C.c_double]
+        L.orc_eps_table_count.restype = C.c_int
         _lib = L
     return _lib
 
@@ -74,7 +78,7 @@ class OracleSim:
     """
 
     def __init__(self, dim, shape, tau, wall_y=False, fluid_force=(0, 0, 0),
-                 particle_accel=(0, 0, 0), samples=4, kn=0.0, restitution=0.9):
+                 particle_accel=(0, 0, 0), samples=4, kn=0.0, restitution=0.9, eps="sampling"):
         nx, ny = shape[0], shape[1]
         nz = shape[2] if dim == 3 else 1
         self.dim, self.nx, self.ny, self.nz = dim, nx, ny, nz
@@ -88,6 +92,9 @@ class OracleSim:
         if not h:
             raise ValueError("oracle rejected the configuration")
         self._h = h
+        if eps not in ("sampling", "table"):
+            raise ValueError("eps must be 'sampling' or 'table'")
+        self._eps = 1 if eps == "table" else 0
 
     def close(self):
         if self._h:
@@ -123,6 +130,8 @@ class OracleSim:
         if rc != 0:
             raise ValueError("oracle rejected the particles")
         self.np_ = n
+        if self._eps == 1 and lib().orc_set_eps_mode(self._h, 1) != 0:
+            raise ValueError("table lookup needs one particle radius of at least 1")
 
     def set_f(self, f):
         f = _f64(f).reshape(self.Q, self.N)
@@ -226,3 +235,12 @@ D3Q19_W = np.array([1 / 3] + [1 / 18] * 6 + [1 / 36] * 12)
 
 def velocities(dim):
     return (D2Q9_C, D2Q9_W) if dim == 2 else (D3Q19_C, D3Q19_W)
+
+
+def eps_table_count(dim, samples, radius, d):
+    """Count on the samples^dim scale that the eps lookup table gives a node
+    at displacement d = (dx, dy, dz) from the centre of a particle of the
+    given radius."""
+    d = list(d) + [0.0] * (3 - len(d))
+    return lib().orc_eps_table_count(int(dim), int(samples), float(radius), float(d[0]), float(d[1]),
+                                     float(d[2]))

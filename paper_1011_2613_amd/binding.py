@@ -20,6 +20,7 @@ LBM_HOST, LBM_DEVICE = 0, 1
 LBM_NPHASES = 6
 PHASES = ("footprint", "lattice", "force", "cells", "dem", "integrate")
 STORAGE = {"fp64": LBM_FP64, "fp32s": LBM_FP32_SHIFTED, "fp16s": LBM_FP16_STORE}
+EPS_MODES = {"sampling": 0, "table": 1}
 ERRORS = {-1: "LBM_E_INVALID", -2: "LBM_E_NOMEM", -3: "LBM_E_HIP", -4: "LBM_E_NONFINITE",
           -5: "LBM_E_SLOT_OVERFLOW", -6: "LBM_E_STATE", -7: "LBM_E_IO",
           -8: "LBM_E_CELL_OVERFLOW", -9: "LBM_E_CONTACT_OVERFLOW"}
@@ -30,7 +31,7 @@ class lbm_config(C.Structure):
                 ("nz", C.c_int), ("wall_y", C.c_int), ("tau", C.c_double),
                 ("fluid_force", C.c_double * 3), ("particle_accel", C.c_double * 3),
                 ("eps_samples", C.c_int), ("kn", C.c_double), ("restitution", C.c_double),
-                ("max_particles", C.c_int), ("max_radius", C.c_double)]
+                ("max_particles", C.c_int), ("max_radius", C.c_double), ("eps_mode", C.c_int)]
 
 
 class LbmError(RuntimeError):
@@ -124,7 +125,7 @@ class Simulation:
 
     def __init__(self, dim, shape, tau, storage="fp64", wall_y=False, fluid_force=(0, 0, 0),
                  particle_accel=(0, 0, 0), samples=4, kn=0.0, restitution=0.9,
-                 max_particles=1, max_radius=0.0, device="cuda:0"):
+                 max_particles=1, max_radius=0.0, eps="sampling", device="cuda:0"):
         import torch
         self._torch = torch
         L = load()
@@ -150,6 +151,7 @@ class Simulation:
         cfg.restitution = float(restitution)
         cfg.max_particles = int(max_particles)
         cfg.max_radius = float(max_radius)
+        cfg.eps_mode = EPS_MODES[eps]
         self.cfg = cfg
         nbytes = C.c_size_t(0)
         self._check(L.lbm_workspace_bytes(C.byref(cfg), C.byref(nbytes)))

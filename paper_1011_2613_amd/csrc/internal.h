@@ -47,6 +47,11 @@ constexpr int MAX_CONTACTS = 32;
 constexpr int CELL_CAP = 16;
 constexpr int SLOT_COUNT_BITS = 10;  // count of sub-samples (<= 512) in the low bits
 
+// eps lookup table (Eq. 6): bins of rho = |r| - R and of the folded direction
+constexpr int EPS_TAB_NRHO = 64;
+constexpr int EPS_TAB_NT = 16;
+constexpr int EPS_TAB_M = 16;  // reference points per axis behind each entry
+
 // Particle state, structure of arrays, binary64.  Vectors are [3][P].
 struct Particles {
     double *x, *v, *w;     // position, velocity, angular velocity
@@ -126,6 +131,10 @@ struct FootArgs {
     uint32_t *slots;
     int S;
     uint32_t *flags;
+    // table lookup of eps (null: sub-cell sampling); H = sqrt(D)/2, the rho
+    // bin width and the direction scales sqrt(2) NT and sqrt(3) NT
+    const uint16_t *tab;
+    double tabH, tabW, tabK1, tabK2;
 };
 
 struct ForceArgs {

@@ -151,6 +151,38 @@ __device__ __forceinline__ int classify(double d0, double d1, double d2, double 
     return -1;
 }
 
+// Table-lookup eps (Eq. 6): the count of a node at displacement (d0, d1, d2)
+// from the centre, from rho = |r| - R and the folded direction of r (sorted
+// magnitudes a >= b >= c, t1 = b/|r|, t2 = c/|r|); wholly inside for
+// rho <= -H, outside for rho >= H (H = sqrt(D)/2, half a cell diagonal).
+template <int D, int SMAX>
+__device__ __forceinline__ int eps_lookup(const FootArgs &a, double d0, double d1, double d2, double R) {
+    double r2 = d0 * d0 + d1 * d1;
+    if (D == 3) r2 = r2 + d2 * d2;
+    // wholly inside or outside by a relative margin of 1e-12 on |r|^2 (far
+    // above the rounding of sqrt(|r|^2) - R): the same decision as below
+    // without the square root
+    const double ri = R - a.tabH, ro = R + a.tabH;
+    if (r2 < ri * ri * (1.0 - 1e-12)) return SMAX;
+    if (r2 > ro * ro * (1.0 + 1e-12)) return 0;
+    const double r = sqrt(r2);
+    const double rho = r - R;
+    if (rho <= -a.tabH) return SMAX;
+    if (rho >= a.tabH) return 0;
+    int ir = (int)floor((rho + a.tabH) / a.tabW);
+    ir = ir < 0 ? 0 : (ir > EPS_TAB_NRHO - 1 ? EPS_TAB_NRHO - 1 : ir);
+    double x = fabs(d0), y = fabs(d1), z = D == 3 ? fabs(d2) : 0.0, t;
+    if (y > x) { t = x; x = y; y = t; }
+    if (z > y) { t = y; y = z; z = t; }
+    if (y > x) { t = x; x = y; y = t; }
+    int i1 = (int)floor(y / r * a.tabK1);
+    i1 = i1 > EPS_TAB_NT - 1 ? EPS_TAB_NT - 1 : i1;
+    if (D == 2) return a.tab[ir * EPS_TAB_NT + i1];
+    int i2 = (int)floor(z / r * a.tabK2);
+    i2 = i2 > EPS_TAB_NT - 1 ? EPS_TAB_NT - 1 : i2;
+    return a.tab[(ir * EPS_TAB_NT + i1) * EPS_TAB_NT + i2];
+}
+
 // Footprint of one particle, one workgroup.  The bounding box is taken in
 // chunks of nodes: (A) every node is classified by distance bounds, undecided
 // nodes are queued in LDS; (B) the queued nodes get the exact per-sample count,
@@ -215,9 +247,12 @@ __global__ __launch_bounds__(NT) void k_foot_paint(FootArgs a) {
             int kx, ky, kz, ix, iy, iz;
             node_of(c0 + i, kx, ky, kz, ix, iy, iz);
             int cls = 0;
-            if (iy >= 0)
-                cls = classify<D, S>(ndisp(a.g, 0, ix, xp0), ndisp(a.g, 1, iy, xp1),
-                                     D == 3 ? ndisp(a.g, 2, iz, xp2) : 0.0, R2);
+            if (iy >= 0) {
+                const double d0 = ndisp(a.g, 0, ix, xp0), d1 = ndisp(a.g, 1, iy, xp1);
+                const double d2 = D == 3 ? ndisp(a.g, 2, iz, xp2) : 0.0;
+                cls = a.tab ? eps_lookup<D, D == 3 ? S * S * S : S * S>(a, d0, d1, d2, r)
+                            : classify<D, S>(d0, d1, d2, R2);
+            }
             if (cls < 0) s_todo[atomicAdd(&s_ntodo, 1)] = (uint16_t)i;
             else s_cnt[i] = (uint16_t)cls;
         }

@@ -39,7 +39,7 @@ struct Layout {
     size_t off_list, off_list_len;
     int list_cap;
     double rmax;
-    size_t off_cc, off_cid, off_flags, total;
+    size_t off_cc, off_cid, off_flags, off_tab, total;
 };
 
 int validate(const lbm_config *c, std::string &msg) {
@@ -52,6 +52,7 @@ int validate(const lbm_config *c, std::string &msg) {
     if ((int64_t)c->nx * c->ny * c->nz >= ((int64_t)1 << 40)) { msg = "lattice too large"; return LBM_E_INVALID; }
     if (!(c->tau > 0.5) || !std::isfinite(c->tau)) { msg = "tau must be > 1/2"; return LBM_E_INVALID; }
     if (c->eps_samples < 1 || c->eps_samples > 8) { msg = "eps_samples must be in 1..8"; return LBM_E_INVALID; }
+    if (c->eps_mode != LBM_EPS_SAMPLING && c->eps_mode != LBM_EPS_TABLE) { msg = "unknown eps_mode"; return LBM_E_INVALID; }
     if (c->max_particles < 0 || c->max_particles > LBM_MAX_PARTICLES) { msg = "max_particles out of range"; return LBM_E_INVALID; }
     if (!(c->restitution > 0.0 && c->restitution <= 1.0)) { msg = "restitution must be in (0, 1]"; return LBM_E_INVALID; }
     if (!(c->kn >= 0.0)) { msg = "kn must be >= 0"; return LBM_E_INVALID; }
@@ -104,6 +105,7 @@ Layout make_layout(const lbm_config *c) {
     L.off_cc = take((size_t)L.cell_budget * 4);
     L.off_cid = take((size_t)L.cell_budget * CELL_CAP * 4);
     L.off_flags = take(64);
+    L.off_tab = take((size_t)EPS_TAB_NRHO * EPS_TAB_NT * EPS_TAB_NT * 2);
     L.total = o;
     return L;
 }
@@ -214,7 +216,67 @@ FootArgs foot_args(lbm_ctx *c) {
     a.slots = wsp<uint32_t>(c, c->L.off_slots);
     a.S = c->cfg.eps_samples;
     a.flags = flags(c);
+    const int D = c->L.D;
+    a.tab = c->cfg.eps_mode == LBM_EPS_TABLE ? wsp<uint16_t>(c, c->L.off_tab) : nullptr;
+    a.tabH = std::sqrt((double)D) * 0.5;
+    a.tabW = 2.0 * a.tabH / (double)EPS_TAB_NRHO;
+    a.tabK1 = std::sqrt(2.0) * (double)EPS_TAB_NT;
+    a.tabK2 = std::sqrt(3.0) * (double)EPS_TAB_NT;
     return a;
+}
+
+// Counts of the eps lookup table for radius R, layout [rho][t1][t2] (t2 only
+// in 3D): the entry of a bin is the number of EPS_TAB_M^D reference points of
+// the cell centred at the bin centre that lie inside the particle, put on the
+// S^D scale with integer rounding (see LBM_EPS_TABLE in the header).
+void build_eps_table(int D, int S, double R, std::vector<uint16_t> &tab) {
+    const double H = std::sqrt((double)D) * 0.5;
+    const double W = 2.0 * H / (double)EPS_TAB_NRHO;
+    const double K1 = std::sqrt(2.0) * (double)EPS_TAB_NT, K2 = std::sqrt(3.0) * (double)EPS_TAB_NT;
+    const int64_t smax = D == 3 ? (int64_t)S * S * S : (int64_t)S * S;
+    const int M = EPS_TAB_M;
+    const int64_t mtot = D == 3 ? (int64_t)M * M * M : (int64_t)M * M;
+    const int n2 = D == 3 ? EPS_TAB_NT : 1;
+    tab.assign((size_t)EPS_TAB_NRHO * EPS_TAB_NT * EPS_TAB_NT, 0);
+    double off[EPS_TAB_M];
+    for (int k = 0; k < M; k++) off[k] = ((double)k + 0.5) / (double)M - 0.5;
+    const double R2 = R * R;
+    for (int ir = 0; ir < EPS_TAB_NRHO; ir++)
+        for (int i1 = 0; i1 < EPS_TAB_NT; i1++)
+            for (int i2 = 0; i2 < n2; i2++) {
+                const double rn = R + (-H + ((double)ir + 0.5) * W);
+                const double b = ((double)i1 + 0.5) / K1 * rn;
+                const double c3 = D == 3 ? ((double)i2 + 0.5) / K2 * rn : 0.0;
+                const double a2 = rn * rn - b * b - c3 * c3;
+                const double a = a2 > 0.0 ? std::sqrt(a2) : 0.0;
+                int64_t kin = 0;
+                for (int kz = 0; kz < (D == 3 ? M : 1); kz++)
+                    for (int ky = 0; ky < M; ky++)
+                        for (int kx = 0; kx < M; kx++) {
+                            const double dx = a + off[kx], dy = b + off[ky];
+                            double r2 = dx * dx + dy * dy;
+                            if (D == 3) {
+                                const double dz = c3 + off[kz];
+                                r2 = r2 + dz * dz;
+                            }
+                            if (r2 <= R2) kin++;
+                        }
+                tab[((size_t)ir * EPS_TAB_NT + i1) * n2 + i2] = (uint16_t)((kin * smax + mtot / 2) / mtot);
+            }
+}
+
+// Table-lookup eps: one radius (>= 1) for every particle; builds and uploads
+// the table for it.
+int upload_eps_table(lbm_ctx *c, const double *radius, int np) {
+    if (np < 1) return LBM_OK;
+    const double R = radius[0];
+    for (int p = 1; p < np; p++)
+        if (radius[p] != R) return fail(c, LBM_E_INVALID, "table-lookup eps needs one particle radius");
+    if (!(R >= 1.0)) return fail(c, LBM_E_INVALID, "table-lookup eps needs a radius of at least 1");
+    std::vector<uint16_t> tab;
+    build_eps_table(c->L.D, c->cfg.eps_samples, R, tab);
+    HIPCHK(c, hipMemcpy(wsp<uint16_t>(c, c->L.off_tab), tab.data(), tab.size() * 2, hipMemcpyHostToDevice));
+    return LBM_OK;
 }
 
 LBArgs lb_args(lbm_ctx *c, int from) {
@@ -555,6 +617,10 @@ int lbm_set_particles(lbm_ctx *c, int64_t n, const double *pos, const double *ve
             return fail(c, LBM_E_INVALID, "particle %d: centre beyond a wall", p);
         rmax = std::max(rmax, r);
     }
+    if (c->cfg.eps_mode == LBM_EPS_TABLE) {
+        const int r = upload_eps_table(c, radius, P);
+        if (r != LBM_OK) return r;
+    }
     // DEM cells: edge >= 2 R_max, count bounded by the reserved budget
     int nc[3] = {1, 1, 1};
     if (P > 0) {
@@ -891,8 +957,10 @@ int lbm_load(lbm_ctx *c, const char *path) {
         if (ok && hipMemcpy(c->ws + o, buf.data(), 3 * P * 8, hipMemcpyHostToDevice) != hipSuccess) ok = false;
     }
     const size_t offs1[] = {c->L.off_R, c->L.off_m, c->L.off_I};
+    std::vector<double> radii(P);
     for (size_t o : offs1) {
         get(buf.data(), P * 8);
+        if (o == c->L.off_R) memcpy(radii.data(), buf.data(), P * 8);
         if (ok && hipMemcpy(c->ws + o, buf.data(), P * 8, hipMemcpyHostToDevice) != hipSuccess) ok = false;
     }
     get(buf.data(), P);
@@ -900,6 +968,10 @@ int lbm_load(lbm_ctx *c, const char *path) {
     get(&c->ncx, 4); get(&c->ncy, 4); get(&c->ncz, 4);
     fclose(fp);
     if (!ok) return fail(c, LBM_E_IO, "read failed: %s", path);
+    if (c->cfg.eps_mode == LBM_EPS_TABLE) {
+        const int r = upload_eps_table(c, radii.data(), np);
+        if (r != LBM_OK) return r;
+    }
     c->cur = 0;
     c->t = t;
     c->particles_set = true;

@@ -17,15 +17,16 @@ def rel_err(a, b):
 
 def make_pair(binding, dim, shape, tau, wall_y=False, fluid_force=(0, 0, 0),
               particle_accel=(0, 0, 0), samples=4, kn=0.0, restitution=0.9,
-              particles=None, f0=None, storage="fp64", max_radius=0.0):
+              particles=None, f0=None, storage="fp64", max_radius=0.0, eps="sampling"):
     """Oracle and GPU simulations with identical inputs."""
     orc = O.OracleSim(dim, shape, tau, wall_y=wall_y, fluid_force=fluid_force,
-                      particle_accel=particle_accel, samples=samples, kn=kn, restitution=restitution)
+                      particle_accel=particle_accel, samples=samples, kn=kn, restitution=restitution,
+                      eps=eps)
     n = 0 if particles is None else len(particles[0])
     gpu = binding.Simulation(dim, shape, tau, storage=storage, wall_y=wall_y,
                              fluid_force=fluid_force, particle_accel=particle_accel,
                              samples=samples, kn=kn, restitution=restitution,
-                             max_particles=max(n, 1), max_radius=max_radius)
+                             max_particles=max(n, 1), max_radius=max_radius, eps=eps)
     if particles is not None and n > 0:
         orc.set_particles(*particles)
         gpu.set_particles(*particles)

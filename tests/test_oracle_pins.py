@@ -514,3 +514,82 @@ def test_table2_masses_and_contact_time(col, dim):
     assert abs(steps_in_contact - tc) <= 1.0
     e_eff = -rel[-1] / rel[0]
     assert abs(e_eff - e) < 0.01
+
+
+# ---------------------------------------------- eps by table lookup (Eq. 6)
+def _fine_coverage(dim, R, d, M=32):
+    """Coverage of the unit cell at displacement d from the centre by M^D
+    points, written out here (not the oracle's sampling routine)."""
+    o = (np.arange(M) + 0.5) / M - 0.5
+    if dim == 2:
+        X, Y = np.meshgrid(d[0] + o, d[1] + o, indexing="ij")
+        return float(((X * X + Y * Y) <= R * R).mean())
+    X, Y, Z = np.meshgrid(d[0] + o, d[1] + o, d[2] + o, indexing="ij")
+    return float(((X * X + Y * Y + Z * Z) <= R * R).mean())
+
+
+@pytest.mark.parametrize("dim,S", [(2, 8), (3, 4)])
+def test_eps_table_planar_limit(dim, S):
+    """For a radius much larger than the cell the surface is a plane: a cell
+    at signed distance rho along an axis is covered 1/2 - rho, along the 2D
+    diagonal (1/sqrt(2) - rho)^2 ... (piecewise quadratic).  The table is
+    within its bin width plus its reference resolution (1/16) of that."""
+    R = 1000.0
+    Smax = S ** dim
+    for rho in np.linspace(-0.48, 0.48, 25):
+        d = [R + rho, 0.0, 0.0]
+        cov = O.eps_table_count(dim, S, R, d) / Smax
+        assert abs(cov - (0.5 - rho)) <= 0.05, (rho, cov)
+    if dim == 2:
+        for rho in np.linspace(-0.68, 0.68, 25):
+            u = (R + rho) / math.sqrt(2.0)
+            cov = O.eps_table_count(2, S, R, [u, u]) / Smax
+            s = -rho      # cell points with n.x <= s are inside
+            h = 1.0 / math.sqrt(2.0)
+            exact = (s + h) ** 2 if s <= 0 else 1.0 - (h - s) ** 2
+            assert abs(cov - exact) <= 0.06, (rho, cov, exact)
+
+
+@pytest.mark.parametrize("dim,S,R", [(2, 8, 6.0), (3, 4, 4.0)])
+def test_eps_table_total_volume(dim, S, R):
+    """The counts of all nodes around a particle add up to its area/volume
+    (pi R^2, 4/3 pi R^3) within 1 %."""
+    c = np.array([0.37, -0.21, 0.13])[:dim]
+    n = int(R) + 2
+    tot = 0
+    rng = range(-n, n + 1)
+    for ix in rng:
+        for iy in rng:
+            for iz in (rng if dim == 3 else [0]):
+                d = np.array([ix, iy, iz][:dim], dtype=float) - c
+                tot += O.eps_table_count(dim, S, R, list(d))
+    vol = tot / S ** dim
+    exact = math.pi * R * R if dim == 2 else 4.0 / 3.0 * math.pi * R ** 3
+    assert abs(vol - exact) / exact < 0.01, (vol, exact)
+
+
+@pytest.mark.parametrize("dim,S,R", [(2, 8, 5.0), (3, 4, 4.0)])
+def test_eps_table_vs_fine_coverage(dim, S, R):
+    """Near the surface the table agrees with a 32^D-point coverage within
+    0.06 per node and 0.01 on average: half a rho bin (sqrt(D)/64) times the
+    slope of the coverage, the 1/16 reference grid and the rounding to the
+    S^D scale bound it.  Sub-cell sampling with S points per axis is printed
+    beside it for comparison."""
+    rs = np.random.default_rng(3)
+    et, es = [], []
+    sim = O.OracleSim(dim, [32] * dim, 0.8, samples=S)
+    for _ in range(150):
+        u = rs.normal(size=dim)
+        u /= np.linalg.norm(u)
+        d = u * (R + rs.uniform(-0.85, 0.85))
+        fine = _fine_coverage(dim, R, d)
+        tab = O.eps_table_count(dim, S, R, list(d)) / S ** dim
+        c = (16.0 - d) if dim == 3 else np.append(16.0 - d, 0.0)
+        sim.set_particles([list(c)], radius=[R], rho_s=[1.0])
+        smp = sim.particle_node_count(0, 16, 16, 16 if dim == 3 else 0) / S ** dim
+        et.append(abs(tab - fine))
+        es.append(abs(smp - fine))
+    sim.close()
+    print("eps error vs 32^D coverage: table mean %.4f max %.4f, sampling mean %.4f max %.4f"
+          % (np.mean(et), np.max(et), np.mean(es), np.max(es)))
+    assert max(et) <= 0.06 and np.mean(et) <= 0.01

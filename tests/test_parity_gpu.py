@@ -150,6 +150,35 @@ def test_large_mixed_particles_many_chunks(gpu_lib):
         assert_close(compare(orc, gpu), label="large discs t=%d" % orc.t)
 
 
+@pytest.mark.parametrize("dim", [2, 3])
+def test_table_lookup_eps_parity(gpu_lib, dim):
+    """The paper's table-lookup solid fraction (Eq. 6): the library's table
+    (built on the host) and lookup (in the footprint kernel) against the
+    oracle's own, moving particles, walls in y, every field compared."""
+    if dim == 3:
+        box = (40, 36, 24)
+        parts = spheres(box, 4.0, 8, 71, 0.01)
+        kw = dict(samples=4, fluid_force=(2e-6, 0, 1e-6))
+    else:
+        box = (96, 64)
+        pos = I.place_particles(2, box, 6.0, 10, 72, wall_y=True)
+        vel = I.random_velocities(2, 10, 0.01, 73)
+        om = np.zeros((10, 3)); om[:, 2] = 1e-3
+        parts = (pos, vel, om, np.full(10, 6.0), np.full(10, 3.0), np.zeros(10, np.uint8))
+        kw = dict(samples=8, fluid_force=(2e-6, 0, 0))
+    say("table eps", dim, box)
+    orc, gpu = make_pair(gpu_lib, dim, box, 0.62, wall_y=True, particle_accel=(0, -2e-5, 0), kn=500.0,
+                         restitution=0.8, particles=parts, eps="table", **kw)
+    for chunk in (1, 40):
+        orc.step(chunk)
+        gpu.step(chunk)
+        assert_close(compare(orc, gpu), label="table eps %dD t=%d" % (dim, orc.t))
+    # a second particle radius is refused in table mode
+    pos2 = np.array(parts[0][:2]); rad2 = np.array([parts[3][0], parts[3][0] + 1.0])
+    with pytest.raises(gpu_lib.LbmError):
+        gpu.set_particles(pos2, radius=rad2, rho_s=np.ones(2))
+
+
 def hex_pack(box, R, rows, gap=-0.2, y0=None, seed=0, v=0.01):
     """Discs in a hexagonal packing resting on the lower wall, neighbours
     overlapping by -gap, with seeded random velocities."""
