@@ -190,7 +190,7 @@ __device__ __forceinline__ int eps_lookup(const FootArgs &a, double d0, double d
 // lists the covered nodes of the chunk in node order (x fastest); (C2) the
 // k-th covered node takes place k of the particle's list and an owner slot, so
 // the list is the same on every run.
-template <int D, int S, int NT>
+template <int D, int S, int NT, bool TAB>
 __global__ __launch_bounds__(NT) void k_foot_paint(FootArgs a) {
     constexpr int CHUNK = 1024;
     __shared__ uint16_t s_cnt[CHUNK];
@@ -250,8 +250,8 @@ __global__ __launch_bounds__(NT) void k_foot_paint(FootArgs a) {
             if (iy >= 0) {
                 const double d0 = ndisp(a.g, 0, ix, xp0), d1 = ndisp(a.g, 1, iy, xp1);
                 const double d2 = D == 3 ? ndisp(a.g, 2, iz, xp2) : 0.0;
-                cls = a.tab ? eps_lookup<D, D == 3 ? S * S * S : S * S>(a, d0, d1, d2, r)
-                            : classify<D, S>(d0, d1, d2, R2);
+                if (TAB) cls = eps_lookup<D, D == 3 ? S * S * S : S * S>(a, d0, d1, d2, r);
+                else cls = classify<D, S>(d0, d1, d2, R2);
             }
             if (cls < 0) s_todo[atomicAdd(&s_ntodo, 1)] = (uint16_t)i;
             else s_cnt[i] = (uint16_t)cls;
@@ -727,26 +727,28 @@ __global__ __launch_bounds__(256) void k_dem(CellArgs a) {
 // ---------------------------------------------------------------- launchers
 static unsigned blocks_for(int n, int per) { return (unsigned)((n + per - 1) / per); }
 
-template <int D, int NT>
+template <int D, int NT, bool TAB>
 static hipError_t paint_s(const FootArgs &a, hipStream_t s) {
     const dim3 g((unsigned)a.P.np), b((unsigned)NT);
     switch (a.S) {
-        case 1: hipLaunchKernelGGL((k_foot_paint<D, 1, NT>), g, b, 0, s, a); break;
-        case 2: hipLaunchKernelGGL((k_foot_paint<D, 2, NT>), g, b, 0, s, a); break;
-        case 3: hipLaunchKernelGGL((k_foot_paint<D, 3, NT>), g, b, 0, s, a); break;
-        case 4: hipLaunchKernelGGL((k_foot_paint<D, 4, NT>), g, b, 0, s, a); break;
-        case 5: hipLaunchKernelGGL((k_foot_paint<D, 5, NT>), g, b, 0, s, a); break;
-        case 6: hipLaunchKernelGGL((k_foot_paint<D, 6, NT>), g, b, 0, s, a); break;
-        case 7: hipLaunchKernelGGL((k_foot_paint<D, 7, NT>), g, b, 0, s, a); break;
-        default: hipLaunchKernelGGL((k_foot_paint<D, 8, NT>), g, b, 0, s, a); break;
+        case 1: hipLaunchKernelGGL((k_foot_paint<D, 1, NT, TAB>), g, b, 0, s, a); break;
+        case 2: hipLaunchKernelGGL((k_foot_paint<D, 2, NT, TAB>), g, b, 0, s, a); break;
+        case 3: hipLaunchKernelGGL((k_foot_paint<D, 3, NT, TAB>), g, b, 0, s, a); break;
+        case 4: hipLaunchKernelGGL((k_foot_paint<D, 4, NT, TAB>), g, b, 0, s, a); break;
+        case 5: hipLaunchKernelGGL((k_foot_paint<D, 5, NT, TAB>), g, b, 0, s, a); break;
+        case 6: hipLaunchKernelGGL((k_foot_paint<D, 6, NT, TAB>), g, b, 0, s, a); break;
+        case 7: hipLaunchKernelGGL((k_foot_paint<D, 7, NT, TAB>), g, b, 0, s, a); break;
+        default: hipLaunchKernelGGL((k_foot_paint<D, 8, NT, TAB>), g, b, 0, s, a); break;
     }
     return hipGetLastError();
 }
 
 hipError_t launch_foot_paint(const FootArgs &a, int D, hipStream_t s) {
     if (a.P.np == 0) return hipSuccess;
-    // two wavefronts per particle (measured faster than four)
-    return D == 2 ? paint_s<2, 128>(a, s) : paint_s<3, 128>(a, s);
+    // two wavefronts per particle (measured faster than four); the table
+    // lookup is a kernel of its own, so the sampling kernel keeps its registers
+    if (a.tab) return D == 2 ? paint_s<2, 128, true>(a, s) : paint_s<3, 128, true>(a, s);
+    return D == 2 ? paint_s<2, 128, false>(a, s) : paint_s<3, 128, false>(a, s);
 }
 
 hipError_t launch_force(const ForceArgs &a, hipStream_t s) {
