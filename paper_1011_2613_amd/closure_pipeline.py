@@ -45,11 +45,18 @@ def run_ensemble(boxes, samples=4, max_steps=20000, check_every=500, tol=1e-5, t
     t2 = time.perf_counter()
     U = b.mean_velocity()
     X, y, box_of = E.drag_dataset(boxes, b, steady, U)
+    # the raw per-box and per-particle results the features are made from
+    F, _ = b.forces()
+    raw = {"edge": np.array([bx["edge"] for bx in boxes]), "radius": np.array([bx["radius"] for bx in boxes]),
+           "tau": np.array([bx["tau"] for bx in boxes]), "count": np.array([len(bx["pos"]) for bx in boxes]),
+           "U": np.asarray(U, dtype=np.float64), "steady": np.asarray(steady, dtype=bool),
+           "pos": np.concatenate([np.asarray(bx["pos"], dtype=np.float64) for bx in boxes]),
+           "Us": np.asarray(b.shell_velocity(), dtype=np.float64), "F": np.asarray(F, dtype=np.float64)}
     updates = float((nodes * stop).sum())
     stats = {"boxes": len(boxes), "steady_boxes": int(steady.sum()), "samples": int(len(y)),
              "node_updates": updates, "run_s": t2 - t1, "setup_s": t1 - t0,
              "mlups": updates / (t2 - t1) / 1e6, "mean_stop_step": float(np.mean(stop)),
-             "tile_rows": tune["rows"], "mode": tune["mode"]}
+             "tile_rows": tune["rows"], "mode": tune["mode"], "raw": raw}
     del b
     return X, y, box_of, stats
 
@@ -68,12 +75,15 @@ def main(argv=None):
     ap.add_argument("--infer-rows", type=int, default=1 << 20)
     ap.add_argument("--out", default=None)
     ap.add_argument("--tune-cache", default=None, help="JSON file of tuned tile shapes (read and written)")
+    ap.add_argument("--save-raw", default=None,
+                    help="npz file for the raw results (box parameters, mean velocities, particle "
+                         "positions, shell velocities and forces) of every ensemble")
     args = ap.parse_args(argv)
     import torch
     if not torch.cuda.is_available():
         raise SystemExit("closure pipeline: no GPU visible")
 
-    Xs, ys, ens_stats = [], [], []
+    Xs, ys, ens_stats, raws = [], [], [], []
     for e in range(args.ensembles):
         boxes = E.sample_boxes(args.boxes, 1000 + e)
         say("ensemble %d: %d boxes" % (e, len(boxes)))
@@ -83,6 +93,7 @@ def main(argv=None):
             % (st["steady_boxes"], st["boxes"], st["samples"], st["run_s"], st["mlups"]))
         Xs.append(X)
         ys.append(y)
+        raws.append(st.pop("raw"))
         ens_stats.append(st)
     Xtr, ytr = np.concatenate(Xs), np.concatenate(ys)
 
@@ -91,6 +102,14 @@ def main(argv=None):
     Xte, yte, bte, test_stats = run_ensemble(test_boxes, max_steps=args.max_steps, check_every=args.check_every,
                                              tol=args.tol, tune_cache=args.tune_cache)
     say("  steady %d/%d boxes, %d samples" % (test_stats["steady_boxes"], test_stats["boxes"], test_stats["samples"]))
+    raw_test = test_stats.pop("raw")
+    if args.save_raw:
+        arrs = {}
+        for i, r in enumerate(raws + [raw_test]):
+            tag = "train%d" % i if i < len(raws) else "heldout"
+            for k, v in r.items():
+                arrs["%s_%s" % (tag, k)] = v
+        np.savez_compressed(args.save_raw, **arrs)
 
     ok = np.isfinite(ytr) & (ytr > 0)
     Xtr, ytr = Xtr[ok], ytr[ok]

@@ -144,6 +144,9 @@ def run_to_steady(batch, boxes, check_every=500, max_steps=20000, tol=1e-5, mode
     return steady, stop
 
 
+NNEIGH = 16  # nearest neighbours described by position in the closure inputs
+
+
 def features(boxes, U, Us):
     """The 40 per-particle closure inputs and the normalising drag scale.
 
@@ -151,10 +154,12 @@ def features(boxes, U, Us):
     neighbour centres), log10 of the box Reynolds number Re = |U| d / nu with
     U the superficial mean velocity, the local slip (the mean fluid velocity
     in the shell [R + 1, 2R] around the sphere, Us; the spheres are at rest)
-    in the flow-aligned frame over |U| (3), a 32-bin histogram of neighbour
-    centres (4 radial shells r/d in [1, 1.5, 2, 2.5, 3) x 8 octants of the
-    flow-aligned frame, x along U), the box solid fraction, d / L and the
-    nearest surface gap / d.
+    in the flow-aligned frame over |U| (3), the positions of the 16 nearest
+    neighbours (minimum image, nearest first) as the distance along the flow
+    and the distance across it, both over d (32; the drag along the flow does
+    not change under rotation about it; a box with fewer spheres pads with the
+    box edge over d), the box solid fraction, d / L and the nearest surface
+    gap / d.
     Returns X [n, 40] and the Stokes drag scale 3 pi nu d |U| [n].
     """
     rows, scale = [], []
@@ -168,31 +173,28 @@ def features(boxes, U, Us):
         umag = float(np.linalg.norm(u))
         re = umag * d / nu
         ex = u / umag if umag > 0 else np.array([1.0, 0.0, 0.0])
-        ey = np.cross(ex, [0.0, 0.0, 1.0])
-        if np.linalg.norm(ey) < 1e-8:
-            ey = np.cross(ex, [0.0, 1.0, 0.0])
-        ey /= np.linalg.norm(ey)
-        ez = np.cross(ex, ey)
         phi_box = n * 4.0 / 3.0 * math.pi * r ** 3 / L ** 3
         for p in range(n):
             dvec = pos - pos[p]
             dvec -= L * np.round(dvec / L)
             dist = np.linalg.norm(dvec, axis=1)
-            others = np.arange(n) != p
-            hist = np.zeros(32)
-            near = others & (dist < 3.0 * d)
-            for q in np.nonzero(near)[0]:
-                s = int((dist[q] / d - 1.0) / 0.5)
-                if s < 0 or s > 3:
-                    continue
-                v = dvec[q]
-                o = (v @ ex > 0) * 4 + (v @ ey > 0) * 2 + (v @ ez > 0) * 1
-                hist[s * 8 + o] += 1.0
-            n_loc = int(np.count_nonzero(others & (dist < 3.0 * r)))
+            others = np.nonzero(np.arange(n) != p)[0]
+            nearest = others[np.argsort(dist[others], kind="stable")][:NNEIGH]
+            along = dvec[nearest] @ ex
+            across = np.sqrt(np.maximum(dist[nearest] ** 2 - along ** 2, 0.0))
+            nb = np.full(2 * NNEIGH, L / d)
+            nb[0:2 * len(nearest):2] = along / d
+            nb[1:2 * len(nearest):2] = across / d
+            n_loc = int(np.count_nonzero(dist[others] < 3.0 * r))
             phi_loc = n_loc / 27.0
             gap = (dist[others].min() - d) / d if n > 1 else L / d
             us = np.asarray(Us[k]) / max(umag, 1e-300)
-            rows.append([phi_loc, math.log10(max(re, 1e-6)), us @ ex, us @ ey, us @ ez, *hist,
+            ey = np.cross(ex, [0.0, 0.0, 1.0])
+            if np.linalg.norm(ey) < 1e-8:
+                ey = np.cross(ex, [0.0, 1.0, 0.0])
+            ey /= np.linalg.norm(ey)
+            ez = np.cross(ex, ey)
+            rows.append([phi_loc, math.log10(max(re, 1e-6)), us @ ex, us @ ey, us @ ez, *nb,
                          phi_box, d / L, gap])
             scale.append(3.0 * math.pi * nu * d * umag)
             k += 1
