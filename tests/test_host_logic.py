@@ -1,3 +1,6 @@
+"""Host-side logic of the package that needs no GPU: the resolution study's
+extrapolation and the closure's input features."""
+import numpy as np
 
 
 def test_validation_extrapolation_recovers_limit_and_order():
@@ -11,3 +14,30 @@ def test_validation_extrapolation_recovers_limit_and_order():
         assert abs(K - Kinf) < 1e-9 * abs(Kinf) and abs(q - p) < 1e-9
     assert V.extrapolate([4.0, 8.0, 16.0], [1.0, 2.0, 1.5]) == (None, None)
     assert abs(V.hasimoto_K(1e-12) - 1.0) < 1e-3
+
+
+def test_closure_neighbour_features():
+    """The 16 neighbour inputs: nearest first, distance along the mean flow
+    and across it over d (minimum image), padded with L/d when the box holds
+    fewer spheres; the other inputs sit where the evaluation expects them."""
+    import math
+    from paper_1011_2613_amd import ensemble as E
+    L, R = 32, 2.0
+    d = 2 * R
+    pos = np.array([[5.0, 5.0, 5.0], [9.0, 5.0, 5.0], [5.0, 11.0, 5.0], [30.0, 5.0, 8.0]])
+    box = {"pos": pos, "radius": R, "edge": L, "tau": 0.8}
+    U = [np.array([0.02, 0.0, 0.0])]
+    Us = np.zeros((4, 3))
+    X, scale = E.features([box], U, Us)
+    assert X.shape == (4, E.NFEAT)
+    nb = X[0, 5:5 + 2 * E.NNEIGH]
+    # neighbours of sphere 0: (4,0,0) at 4, (-7,0,3) at 7.6 (image of sphere 3), (0,6,0) at 6
+    assert np.allclose(nb[0:2], [4.0 / d, 0.0])
+    assert np.allclose(nb[2:4], [0.0, 6.0 / d])
+    assert np.allclose(nb[4:6], [-7.0 / d, 3.0 / d])
+    assert np.all(nb[6:] == L / d)
+    nu = (0.8 - 0.5) / 3.0
+    assert abs(X[0, 1] - math.log10(0.02 * d / nu)) < 1e-12
+    assert abs(X[0, E.NFEAT - 3] - 4 * 4.0 / 3.0 * math.pi * R ** 3 / L ** 3) < 1e-12
+    assert abs(X[0, E.NFEAT - 1] - (4.0 - d) / d) < 1e-12
+    assert np.allclose(scale, 3 * math.pi * nu * d * 0.02)
