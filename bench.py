@@ -30,9 +30,10 @@ def kernel_source_sha():
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
-def measured_traffic(storage, workload):
+def measured_traffic(storage, workload, width):
     """HBM bytes per launch of the lattice kernel from the committed rocprofv3
-    counter runs, if they were taken on the current kernel source."""
+    counter runs, if they were taken on the current kernel source at the
+    workgroup width in use."""
     path = os.path.join(ROOT, "profiles", "lb_kernel_traffic.json")
     try:
         with open(path) as f:
@@ -42,16 +43,36 @@ def measured_traffic(storage, workload):
     rec = d.get("%s_%s" % (workload, storage))
     if not rec or rec.get("kernel_source_sha") != kernel_source_sha():
         return None
+    if rec.get("lattice_block") != width:
+        return None
     return rec.get("bytes_per_launch")
 
 
-def run_variant(binding, inputs, w, parts, storage, steps, warmup, eps="sampling"):
+def parse_blocks(spec):
+    """--lattice-block: "auto", one width for every variant, or per variant
+    ("fp64=192,fp32s=64")."""
+    if spec == "auto":
+        return {}
+    if "=" not in spec:
+        return {v: int(spec) for v in BYTES_PER_VALUE}
+    return {k: int(x) for k, x in (item.split("=") for item in spec.split(",") if item)}
+
+
+def run_variant(binding, inputs, w, parts, storage, steps, warmup, eps="sampling", block=None):
     import torch
     sim = binding.Simulation(w.dim, w.shape, w.tau, storage=storage, wall_y=w.wall_y,
                              fluid_force=w.fluid_force, particle_accel=w.particle_accel,
                              samples=w.samples, kn=w.kn, restitution=w.restitution,
                              max_particles=w.count, max_radius=w.radius, eps=eps)
     sim.set_particles(*parts)
+    # the lattice kernel's workgroup width: measured per workload and storage
+    # (part of the warm-up), or as given
+    tune_ms = None
+    if block is None:
+        _, tune_ms = sim.autotune_lattice_block(steps=20)
+    else:
+        sim.set_lattice_block(block)
+    width = sim.lattice_block
     sim.step(warmup)
     # timed region: HIP events around the lattice kernel only (on the stream
     # it runs on), the other kernels launched as in normal operation
@@ -74,7 +95,7 @@ def run_variant(binding, inputs, w, parts, storage, steps, warmup, eps="sampling
     Q = 9 if w.dim == 2 else 19
     bpn = 2 * Q * BYTES_PER_VALUE[storage]
     achieved = bpn * w.nodes / (avg_ms * 1e-3) / 1e9
-    traffic = measured_traffic(storage, w.name)
+    traffic = measured_traffic(storage, w.name, width)
     sim.close()
     del sim
     torch.cuda.empty_cache()
@@ -85,6 +106,8 @@ def run_variant(binding, inputs, w, parts, storage, steps, warmup, eps="sampling
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic},
         "phase_ms_per_step": {k: round(v[0] / v[1], 4) for k, v in phases.items() if v[1] > 0},
+        "lattice_block": width,
+        "lattice_block_tuning_ms": None if tune_ms is None else {str(k): round(v, 4) for k, v in tune_ms.items()},
     }
 
 
@@ -182,6 +205,9 @@ def main():
     ap.add_argument("--variants", default="fp64,fp32s,fp16s")
     ap.add_argument("--eps", default="sampling", choices=["sampling", "table"],
                     help="solid fraction by sub-cell sampling or by the paper's table lookup")
+    ap.add_argument("--lattice-block", default="auto",
+                    help='lattice kernel workgroup width: "auto" (measured per variant), '
+                         'one of 64/128/192/256, or per variant, e.g. "fp64=192,fp32s=64"')
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the batched-ensemble and closure measurements")
@@ -204,12 +230,14 @@ def main():
     variants = [v for v in args.variants.split(",") if v]
     if "fp64" not in variants:
         variants = ["fp64"] + variants
+    blocks = parse_blocks(args.lattice_block)
     res = {}
     for v in variants:
-        res[v] = run_variant(binding, inputs, w, parts, v, args.steps, args.warmup, eps=args.eps)
-        print("# %s: %.1f MLUPS, lattice kernel %.3f ms, %.1f GB/s"
-              % (v, res[v]["mlups"], res[v]["lattice_kernel_ms"], res[v]["roofline"]["achieved"]),
-              file=sys.stderr, flush=True)
+        res[v] = run_variant(binding, inputs, w, parts, v, args.steps, args.warmup, eps=args.eps,
+                             block=blocks.get(v))
+        print("# %s: %.1f MLUPS, lattice kernel %.3f ms, %.1f GB/s, workgroup %d"
+              % (v, res[v]["mlups"], res[v]["lattice_kernel_ms"], res[v]["roofline"]["achieved"],
+                 res[v]["lattice_block"]), file=sys.stderr, flush=True)
     base = res["fp64"]
     out = {
         "metric": METRIC,
@@ -227,12 +255,16 @@ def main():
         "config": {"workload": "%s: D3Q19 %dx%dx%d, %s, %d spheres R=%g, tau %g, density ratio %g"
                    % (w.name, *w.shape, "walls y" if w.wall_y else "periodic", w.count, w.radius,
                       round(w.tau, 4), w.rho_ratio),
-                   "nodes": w.nodes, "particles": w.count, "storage": "fp64", "eps": args.eps},
+                   "nodes": w.nodes, "particles": w.count, "storage": "fp64", "eps": args.eps,
+                   "lattice_block": base["lattice_block"],
+                   "lattice_block_tuning_ms": base["lattice_block_tuning_ms"]},
         "roofline": base["roofline"],
         "phase_ms_per_step": base["phase_ms_per_step"],
         "variants": {v: {"value": round(r["mlups"], 1), "unit": "MLUPS", "dtype": DTYPE[v],
                          "ms_per_step": round(r["ms_per_step"], 4),
                          "roofline": r["roofline"], "phase_ms_per_step": r["phase_ms_per_step"],
+                         "lattice_block": r["lattice_block"],
+                         "lattice_block_tuning_ms": r["lattice_block_tuning_ms"],
                          "speedup_vs_fp64": round(r["mlups"] / base["mlups"], 3)}
                      for v, r in res.items() if v != "fp64"},
         "device": torch.cuda.get_device_name(0),

@@ -45,6 +45,7 @@ _SYMBOLS = ("lbm_workspace_bytes", "lbm_create", "lbm_destroy", "lbm_set_particl
             "lbm_set_distributions", "lbm_get_distributions", "lbm_step", "lbm_get_forces",
             "lbm_get_contact_forces", "lbm_get_particles", "lbm_get_macro", "lbm_get_q",
             "lbm_time", "lbm_particle_count", "lbm_set_timing", "lbm_get_timing", "lbm_save", "lbm_load",
+            "lbm_set_lattice_block", "lbm_get_lattice_block", "lbm_autotune_lattice_block",
             "lbm_error_string", "lbm_last_error",
             "mlp_workspace_bytes", "mlp_create", "mlp_destroy", "mlp_set_params", "mlp_get_params",
             "mlp_forward", "mlp_gradients", "mlp_train_step",
@@ -86,6 +87,9 @@ def load():
     L.lbm_particle_count.restype = i64
     L.lbm_set_timing.argtypes = [vp, C.c_int]
     L.lbm_get_timing.argtypes = [vp, dp, C.POINTER(i64)]
+    L.lbm_set_lattice_block.argtypes = [vp, C.c_int]
+    L.lbm_get_lattice_block.argtypes = [vp]
+    L.lbm_autotune_lattice_block.argtypes = [vp, C.c_int, C.POINTER(C.c_int), dp]
     L.lbm_save.argtypes = [vp, C.c_char_p]
     L.lbm_load.argtypes = [vp, C.c_char_p]
     L.lbm_error_string.argtypes = [C.c_int]
@@ -267,6 +271,25 @@ class Simulation:
         n = (C.c_int64 * LBM_NPHASES)()
         self._check(load().lbm_get_timing(self._ctx, ms, n))
         return {PHASES[k]: (ms[k], n[k]) for k in range(LBM_NPHASES)}
+
+    LATTICE_BLOCKS = (64, 128, 192, 256)
+
+    def set_lattice_block(self, threads):
+        """Workgroup width of the lattice kernel (0: built-in rule)."""
+        self._check(load().lbm_set_lattice_block(self._ctx, int(threads)))
+
+    @property
+    def lattice_block(self):
+        return int(load().lbm_get_lattice_block(self._ctx))
+
+    def autotune_lattice_block(self, steps=20):
+        """Time the lattice kernel at each workgroup width over real steps
+        (the state advances by 8 (steps + 1) steps) and keep the fastest.
+        Returns (width, {width: mean ms per lattice launch})."""
+        best = C.c_int(0)
+        ms = (C.c_double * 4)()
+        self._check(load().lbm_autotune_lattice_block(self._ctx, int(steps), C.byref(best), ms))
+        return best.value, {w: ms[k] for k, w in enumerate(self.LATTICE_BLOCKS)}
 
     def save(self, path):
         self._check(load().lbm_save(self._ctx, str(path).encode()))

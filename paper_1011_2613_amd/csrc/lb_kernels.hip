@@ -482,22 +482,37 @@ static dim3 lattice_grid(const Geom &g, int &block) {
 }
 
 template <class L, int ST>
-static hipError_t lb_dispatch(const LBArgs &a, hipStream_t s) {
+static hipError_t lb_dispatch(const LBArgs &a, int width, hipStream_t s) {
     int block;
     dim3 grid = lattice_grid(a.g, block);
+    if (width > 0) {
+        // a chosen workgroup width: part of one row per workgroup, the ragged
+        // end of a row masked by the kernel's x < nx test
+        block = width;
+        grid.x = (unsigned)((a.g.nx + width - 1) / width);
+    }
     hipLaunchKernelGGL((k_lb<L, ST>), grid, dim3(block), 0, s, a);
     return hipGetLastError();
 }
 
-hipError_t launch_lb(int lattice, int storage, const LBArgs &a, hipStream_t s) {
+int lattice_block_width(int nx, int width) {
+    if (width > 0) return width;
+    Geom g{};
+    g.nx = nx;
+    int block;
+    (void)lattice_grid(g, block);
+    return block;
+}
+
+hipError_t launch_lb(int lattice, int storage, const LBArgs &a, int width, hipStream_t s) {
     if (lattice == 0) {
-        if (storage == 0) return lb_dispatch<D2Q9, 0>(a, s);
-        if (storage == 1) return lb_dispatch<D2Q9, 1>(a, s);
-        return lb_dispatch<D2Q9, 2>(a, s);
+        if (storage == 0) return lb_dispatch<D2Q9, 0>(a, width, s);
+        if (storage == 1) return lb_dispatch<D2Q9, 1>(a, width, s);
+        return lb_dispatch<D2Q9, 2>(a, width, s);
     }
-    if (storage == 0) return lb_dispatch<D3Q19, 0>(a, s);
-    if (storage == 1) return lb_dispatch<D3Q19, 1>(a, s);
-    return lb_dispatch<D3Q19, 2>(a, s);
+    if (storage == 0) return lb_dispatch<D3Q19, 0>(a, width, s);
+    if (storage == 1) return lb_dispatch<D3Q19, 1>(a, width, s);
+    return lb_dispatch<D3Q19, 2>(a, width, s);
 }
 
 #define LBIMB_DISPATCH(KERNEL, ...)                                                          \

@@ -139,6 +139,7 @@ struct lbm_ctx {
     hipGraphExec_t graph[2];
     bool graph_ok[2];
     int timing;  // 0 off, 1 every phase, 2 the lattice phase only
+    int lb_width;  // lattice kernel workgroup width, 0 for the built-in rule
     bool rec_open;
     std::vector<TimedEvent> events;
     size_t ev_used;
@@ -349,7 +350,7 @@ hipError_t enqueue_step(lbm_ctx *c, int from, hipStream_t s, int slot) {
         phase_end(c, s);
     }
     phase_begin(c, 1, s);
-    if ((e = launch_lb(lattice, storage, lb_args(c, from), s)) != hipSuccess) return e;
+    if ((e = launch_lb(lattice, storage, lb_args(c, from), c->lb_width, s)) != hipSuccess) return e;
     phase_end(c, s);
     if (c->np > 0) {
         ForceArgs fo;
@@ -500,6 +501,7 @@ int lbm_create(const lbm_config *cfg, void *workspace, size_t ws_bytes, void *hi
     }
     c->graph_ok[0] = c->graph_ok[1] = false;
     c->timing = 0;
+    c->lb_width = 0;
     c->rec_open = false;
     c->ev_used = 0;
     for (int k = 0; k < LBM_NPHASES; k++) { c->phase_ms[k] = 0.0; c->phase_n[k] = 0; }
@@ -891,6 +893,67 @@ int lbm_get_timing(lbm_ctx *c, double *ms, int64_t *launches) {
     }
     c->ev_used = 0;
     for (int k = 0; k < LBM_NPHASES; k++) { ms[k] = c->phase_ms[k]; launches[k] = c->phase_n[k]; }
+    return LBM_OK;
+}
+
+int lbm_set_lattice_block(lbm_ctx *c, int threads) {
+    if (!c) return LBM_E_INVALID;
+    if (!(threads == 0 || threads == 64 || threads == 128 || threads == 192 || threads == 256))
+        return fail(c, LBM_E_INVALID, "lattice block width %d is not 0, 64, 128, 192 or 256", threads);
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    if (threads != c->lb_width) {
+        c->lb_width = threads;
+        drop_graphs(c);  // captured steps hold the old launch shape
+    }
+    return LBM_OK;
+}
+
+int lbm_get_lattice_block(const lbm_ctx *c) {
+    return c ? lattice_block_width(c->cfg.nx, c->lb_width) : LBM_E_INVALID;
+}
+
+// Every width computes the same bits at every node, so the choice is by time
+// alone: each candidate runs real steps with the lattice phase timed, twice in
+// alternating order so that a drift of the clock or of the state between the
+// first and the last candidate does not favour one of them.
+int lbm_autotune_lattice_block(lbm_ctx *c, int steps, int *best_out, double *ms_out) {
+    if (!c || steps < 1 || steps > 100000) return LBM_E_INVALID;
+    static const int widths[4] = {64, 128, 192, 256};
+    const int prev_timing = c->timing, prev_width = c->lb_width;
+    double best_ms[4] = {HUGE_VAL, HUGE_VAL, HUGE_VAL, HUGE_VAL};
+    int r = LBM_OK;
+    for (int pass = 0; pass < 2 && r == LBM_OK; pass++) {
+        for (int j = 0; j < 4 && r == LBM_OK; j++) {
+            const int k = pass == 0 ? j : 3 - j;
+            if ((r = lbm_set_lattice_block(c, widths[k])) != LBM_OK) break;
+            if ((r = lbm_set_timing(c, 2)) != LBM_OK) break;
+            if ((r = lbm_step(c, 1)) != LBM_OK) break;  // first launch of this shape, untimed
+            if ((r = lbm_set_timing(c, 2)) != LBM_OK) break;
+            if ((r = lbm_step(c, steps)) != LBM_OK) break;
+            double ms[LBM_NPHASES];
+            int64_t n[LBM_NPHASES];
+            if ((r = lbm_get_timing(c, ms, n)) != LBM_OK) break;
+            if (n[1] > 0) best_ms[k] = std::min(best_ms[k], ms[1] / (double)n[1]);
+        }
+    }
+    if (r != LBM_OK) {
+        char msg[512];
+        memcpy(msg, c->err, sizeof(msg));
+        (void)lbm_set_lattice_block(c, prev_width);
+        (void)lbm_set_timing(c, prev_timing);
+        memcpy(c->err, msg, sizeof(msg));
+        memcpy(g_err, msg, sizeof(g_err));
+        return r;
+    }
+    int best = 0;
+    for (int k = 1; k < 4; k++)
+        if (best_ms[k] < best_ms[best]) best = k;
+    r = lbm_set_lattice_block(c, widths[best]);
+    if (r == LBM_OK) r = lbm_set_timing(c, prev_timing);
+    if (r != LBM_OK) return r;
+    if (best_out) *best_out = widths[best];
+    if (ms_out)
+        for (int k = 0; k < 4; k++) ms_out[k] = best_ms[k];
     return LBM_OK;
 }
 

@@ -253,6 +253,89 @@ def test_graph_and_eager_agree_bitwise(gpu_lib):
     assert all(n == 0 for k, (ms, n) in t.items() if k != "lattice")
 
 
+@pytest.mark.parametrize("storage", ["fp64", "fp32s", "fp16s"])
+def test_lattice_block_widths_bitwise(gpu_lib, storage):
+    """The lattice kernel's workgroup width changes the launch shape only:
+    every width (the last workgroup of a row overhanging it by up to 170
+    threads) gives the state of the default launch bit for bit, in 3D with
+    walls and moving spheres and in 2D with rows wider than one workgroup."""
+    cases = [(3, (150, 40, 24), spheres((150, 40, 24), 4.0, 10, 51, 0.01)),
+             (2, (300, 48, 1), None)]
+    for dim, box, parts in cases:
+        shape = box if dim == 3 else box[:2]
+        say("lattice widths", storage, shape)
+        kw = dict(storage=storage, wall_y=True, fluid_force=(2e-6, 0, 0), particle_accel=(0, -2e-5, 0),
+                  samples=4, kn=500.0, restitution=0.8, max_particles=10)
+        f0 = seeded_f(dim, int(np.prod(shape)), 0.02, 7)
+        ref = None
+        for width in (0, 64, 128, 192, 256):
+            s = gpu_lib.Simulation(dim, shape, 0.62, **kw)
+            s.set_f(f0)
+            if parts is not None:
+                s.set_particles(*parts)
+            s.set_lattice_block(width)
+            assert s.lattice_block == (width or (192 if box[0] == 150 else 256))
+            s.step(23)
+            got = (s.get_f(), s.particles()[0] if parts is not None else None,
+                   s.forces()[0] if parts is not None else None)
+            s.close()
+            if ref is None:
+                ref = got
+                continue
+            for a, b in zip(got, ref):
+                assert a is None or np.array_equal(a, b), "width %d differs" % width
+
+
+def test_lattice_block_width_fp64_parity(gpu_lib):
+    """A non-default width against the oracle directly (FP64 bar)."""
+    box = (150, 20, 12)
+    parts = spheres(box, 3.0, 6, 61, 0.01)
+    say("width 64 vs oracle")
+    orc, gpu = make_pair(gpu_lib, 3, box, 0.7, wall_y=True, fluid_force=(1e-6, 0, 0),
+                         particle_accel=(0, -1e-5, 0), samples=4, kn=400.0, restitution=0.9,
+                         particles=parts)
+    gpu.set_lattice_block(64)
+    orc.step(6)
+    gpu.step(6)
+    assert_close(compare(orc, gpu), label="width 64 t=6")
+
+
+def test_lattice_block_autotune(gpu_lib):
+    """The autotuner advances the state by 8 (steps + 1) real steps, keeps
+    one of the four widths, restores the timing mode with cleared counters,
+    and the tuned run continues bit for bit like an untuned one."""
+    box = (96, 30, 20)
+    parts = spheres(box, 4.0, 5, 71, 0.01)
+    say("lattice width autotune")
+    kw = dict(storage="fp32s", wall_y=True, fluid_force=(1e-6, 0, 0), particle_accel=(0, -1e-5, 0),
+              samples=4, kn=500.0, restitution=0.9, max_particles=5)
+    a = gpu_lib.Simulation(3, box, 0.65, **kw)
+    a.set_particles(*parts)
+    a.set_timing(True, lattice_only=True)
+    best, ms = a.autotune_lattice_block(steps=3)
+    assert a.t == 8 * 4
+    assert best in (64, 128, 192, 256) and a.lattice_block == best
+    assert sorted(ms) == [64, 128, 192, 256]
+    assert all(math.isfinite(v) and v > 0 for v in ms.values())
+    assert ms[best] == min(ms.values())
+    t = a.get_timing()
+    assert all(n == 0 for _, n in t.values())   # counters cleared, mode kept
+    a.step(5)
+    assert a.get_timing()["lattice"][1] == 5
+    a.set_timing(False)
+    a.step(6)
+    b = gpu_lib.Simulation(3, box, 0.65, **kw)
+    b.set_particles(*parts)
+    b.step(8 * 4 + 11)
+    assert np.array_equal(a.get_f(), b.get_f())
+    assert np.array_equal(a.particles()[0], b.particles()[0])
+    with pytest.raises(gpu_lib.LbmError):
+        a.set_lattice_block(96)
+    with pytest.raises(gpu_lib.LbmError):
+        a.autotune_lattice_block(steps=0)
+    assert a.lattice_block == best
+
+
 def test_save_load_resume_bitwise(gpu_lib):
     box = (40, 36, 24)
     parts = spheres(box, 4.0, 6, 41, 0.01)
