@@ -12,6 +12,7 @@ Prints ONE JSON line.  value = FP64 MLUPS (lattice nodes x steps / wall s).
 import argparse
 import hashlib
 import json
+import math
 import os
 import sys
 import time
@@ -48,14 +49,24 @@ def measured_traffic(storage, workload, width):
     return rec.get("bytes_per_launch")
 
 
+def parse_shape(text):
+    """"256" or "256/xcd" -> (256, "xcd")."""
+    w, _, order = text.partition("/")
+    return int(w), order or "linear"
+
+
 def parse_blocks(spec):
-    """--lattice-block: "auto", one width for every variant, or per variant
-    ("fp64=192,fp32s=64")."""
+    """--lattice-block: "auto", one launch shape for every variant, or per
+    variant ("fp64=192/xcd,fp32s=64")."""
     if spec == "auto":
         return {}
     if "=" not in spec:
-        return {v: int(spec) for v in BYTES_PER_VALUE}
-    return {k: int(x) for k, x in (item.split("=") for item in spec.split(",") if item)}
+        return {v: parse_shape(spec) for v in BYTES_PER_VALUE}
+    return {k: parse_shape(x) for k, x in (item.split("=") for item in spec.split(",") if item)}
+
+
+def shape_text(shape):
+    return "%d/%s" % shape if shape[1] != "linear" else "%d" % shape[0]
 
 
 def run_variant(binding, inputs, w, parts, storage, steps, warmup, eps="sampling", block=None):
@@ -71,8 +82,8 @@ def run_variant(binding, inputs, w, parts, storage, steps, warmup, eps="sampling
     if block is None:
         _, tune_ms = sim.autotune_lattice_block(steps=20)
     else:
-        sim.set_lattice_block(block)
-    width = sim.lattice_block
+        sim.set_lattice_block(*block)
+    width = shape_text(sim.lattice_block)
     sim.step(warmup)
     # timed region: HIP events around the lattice kernel only (on the stream
     # it runs on), the other kernels launched as in normal operation
@@ -107,7 +118,8 @@ def run_variant(binding, inputs, w, parts, storage, steps, warmup, eps="sampling
                      "traffic": traffic},
         "phase_ms_per_step": {k: round(v[0] / v[1], 4) for k, v in phases.items() if v[1] > 0},
         "lattice_block": width,
-        "lattice_block_tuning_ms": None if tune_ms is None else {str(k): round(v, 4) for k, v in tune_ms.items()},
+        "lattice_block_tuning_ms": None if tune_ms is None else {
+            shape_text(k): round(v, 4) for k, v in tune_ms.items() if math.isfinite(v)},
     }
 
 
@@ -206,8 +218,9 @@ def main():
     ap.add_argument("--eps", default="sampling", choices=["sampling", "table"],
                     help="solid fraction by sub-cell sampling or by the paper's table lookup")
     ap.add_argument("--lattice-block", default="auto",
-                    help='lattice kernel workgroup width: "auto" (measured per variant), '
-                         'one of 64/128/192/256, or per variant, e.g. "fp64=192,fp32s=64"')
+                    help='lattice kernel launch shape: "auto" (measured per variant), a width '
+                         '64/128/192/256 with an optional "/xcd" workgroup order, or per variant, '
+                         'e.g. "fp64=192/xcd,fp32s=64"')
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the batched-ensemble and closure measurements")
@@ -235,7 +248,7 @@ def main():
     for v in variants:
         res[v] = run_variant(binding, inputs, w, parts, v, args.steps, args.warmup, eps=args.eps,
                              block=blocks.get(v))
-        print("# %s: %.1f MLUPS, lattice kernel %.3f ms, %.1f GB/s, workgroup %d"
+        print("# %s: %.1f MLUPS, lattice kernel %.3f ms, %.1f GB/s, workgroup %s"
               % (v, res[v]["mlups"], res[v]["lattice_kernel_ms"], res[v]["roofline"]["achieved"],
                  res[v]["lattice_block"]), file=sys.stderr, flush=True)
     base = res["fp64"]

@@ -177,29 +177,39 @@ int64_t lbm_particle_count(const lbm_ctx *ctx);
 int lbm_set_timing(lbm_ctx *ctx, int enable);
 int lbm_get_timing(lbm_ctx *ctx, double *ms, int64_t *launches);
 
-/* Workgroup width of the lattice kernel: threads along x, one workgroup
- * covering all or part of one lattice row (the kernel of the update of Eq. 1
- * with the immersed-boundary terms of Eq. 2).  0 selects the built-in rule
- * (the whole row when nx <= 256, else 256 threads); otherwise 64, 128, 192 or
- * 256 (the end of a row that the last workgroup overhangs is masked).  The
- * width changes the launch shape only: every node gets the same bits.  Takes
- * effect from the next step (captured step graphs are dropped).  Errors:
- * LBM_E_INVALID for another width.  lbm_get_lattice_block returns the width
- * in use, the rule resolved, or LBM_E_INVALID for a null context. */
-int lbm_set_lattice_block(lbm_ctx *ctx, int threads);
-int lbm_get_lattice_block(const lbm_ctx *ctx);
+/* Launch shape of the lattice kernel (the update of Eq. 1 with the
+ * immersed-boundary terms of Eq. 2).  threads: the workgroup width along x,
+ * one workgroup covering all or part of one lattice row; 0 selects the
+ * built-in rule (the whole row when nx <= 256, else 256 threads), otherwise
+ * 64, 128, 192 or 256 (the end of a row that the last workgroup overhangs is
+ * masked).  order: LBM_ORDER_LINEAR hands tiles to workgroups in launch
+ * order; LBM_ORDER_XCD renumbers workgroups so that each of the GPU's 8
+ * XCDs (which the hardware feeds workgroup ids in turn) takes one contiguous
+ * run of tiles, keeping neighbouring rows in one L2.  The launch shape never
+ * changes a bit of the result.  Takes effect from the next step (captured
+ * step graphs are dropped).  Errors: LBM_E_INVALID for another width or
+ * order, or for XCD order on a grid of 2^32 workgroups or more.
+ * lbm_get_lattice_block writes the width in use (the rule resolved) and the
+ * order; LBM_E_INVALID for a null argument. */
+enum { LBM_ORDER_LINEAR = 0, LBM_ORDER_XCD = 1 };
+int lbm_set_lattice_block(lbm_ctx *ctx, int threads, int order);
+int lbm_get_lattice_block(const lbm_ctx *ctx, int *threads, int *order);
 
-/* Chooses the lattice kernel's workgroup width by measurement: each of 64,
- * 128, 192 and 256 threads runs 1 + `steps` real time steps twice (the
- * simulation advances by 8 (1 + steps) steps; results do not depend on the
- * width), the lattice phase timed as in timing mode 2, and the width with the
- * shortest mean lattice kernel time is kept.  best_out (may be null)
- * receives it, ms_out (4 doubles, may be null) the mean milliseconds per
- * lattice launch of each width (the faster of the two passes).  The timing
- * mode in force before the call is restored with its counters cleared.
- * Errors: LBM_E_INVALID for steps outside 1..100000; a failed step returns
- * its code with the previous width and timing mode restored. */
-int lbm_autotune_lattice_block(lbm_ctx *ctx, int steps, int *best_out, double *ms_out);
+/* Chooses the lattice kernel's launch shape by measurement.  Each of the 8
+ * candidates (order k / 4, width 64, 128, 192, 256 for k % 4 = 0..3; XCD
+ * candidates skipped where the grid is too large for them) runs 1 + `steps`
+ * real time steps twice, so the simulation advances by up to 16 (1 + steps)
+ * steps; the result does not depend on the shape.  The lattice phase is
+ * timed as in timing mode 2, and the candidate with the shortest mean
+ * lattice kernel time is kept.  best_threads and best_order (may be null)
+ * receive it; ms_out (8 doubles, may be null) the mean milliseconds per
+ * lattice launch of each candidate (the faster of the two passes; HUGE_VAL
+ * for a skipped one).  The timing mode in force before the call is restored
+ * with its counters cleared.  Errors: LBM_E_INVALID for steps outside
+ * 1..100000; a failed step returns its code with the previous shape and
+ * timing mode restored. */
+int lbm_autotune_lattice_block(lbm_ctx *ctx, int steps, int *best_threads, int *best_order,
+                               double *ms_out);
 
 /* Writes / reads the full state (populations in storage format, particles,
  * forces, time) to / from a file.  The file records the configuration; a

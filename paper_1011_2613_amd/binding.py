@@ -87,9 +87,9 @@ def load():
     L.lbm_particle_count.restype = i64
     L.lbm_set_timing.argtypes = [vp, C.c_int]
     L.lbm_get_timing.argtypes = [vp, dp, C.POINTER(i64)]
-    L.lbm_set_lattice_block.argtypes = [vp, C.c_int]
-    L.lbm_get_lattice_block.argtypes = [vp]
-    L.lbm_autotune_lattice_block.argtypes = [vp, C.c_int, C.POINTER(C.c_int), dp]
+    L.lbm_set_lattice_block.argtypes = [vp, C.c_int, C.c_int]
+    L.lbm_get_lattice_block.argtypes = [vp, C.POINTER(C.c_int), C.POINTER(C.c_int)]
+    L.lbm_autotune_lattice_block.argtypes = [vp, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int), dp]
     L.lbm_save.argtypes = [vp, C.c_char_p]
     L.lbm_load.argtypes = [vp, C.c_char_p]
     L.lbm_error_string.argtypes = [C.c_int]
@@ -273,23 +273,31 @@ class Simulation:
         return {PHASES[k]: (ms[k], n[k]) for k in range(LBM_NPHASES)}
 
     LATTICE_BLOCKS = (64, 128, 192, 256)
+    LATTICE_ORDERS = ("linear", "xcd")
 
-    def set_lattice_block(self, threads):
-        """Workgroup width of the lattice kernel (0: built-in rule)."""
-        self._check(load().lbm_set_lattice_block(self._ctx, int(threads)))
+    def set_lattice_block(self, threads, order="linear"):
+        """Launch shape of the lattice kernel: workgroup width (0: built-in
+        rule) and workgroup order ("linear" or "xcd")."""
+        self._check(load().lbm_set_lattice_block(self._ctx, int(threads),
+                                                 self.LATTICE_ORDERS.index(order)))
 
     @property
     def lattice_block(self):
-        return int(load().lbm_get_lattice_block(self._ctx))
+        """(width, order) of the lattice kernel's launches."""
+        w, o = C.c_int(0), C.c_int(0)
+        self._check(load().lbm_get_lattice_block(self._ctx, C.byref(w), C.byref(o)))
+        return w.value, self.LATTICE_ORDERS[o.value]
 
     def autotune_lattice_block(self, steps=20):
-        """Time the lattice kernel at each workgroup width over real steps
-        (the state advances by 8 (steps + 1) steps) and keep the fastest.
-        Returns (width, {width: mean ms per lattice launch})."""
-        best = C.c_int(0)
-        ms = (C.c_double * 4)()
-        self._check(load().lbm_autotune_lattice_block(self._ctx, int(steps), C.byref(best), ms))
-        return best.value, {w: ms[k] for k, w in enumerate(self.LATTICE_BLOCKS)}
+        """Time the lattice kernel at each width and order over real steps
+        (the state advances by up to 16 (steps + 1) steps) and keep the
+        fastest.  Returns ((width, order), {(width, order): mean ms per
+        lattice launch})."""
+        w, o = C.c_int(0), C.c_int(0)
+        ms = (C.c_double * 8)()
+        self._check(load().lbm_autotune_lattice_block(self._ctx, int(steps), C.byref(w), C.byref(o), ms))
+        table = {(self.LATTICE_BLOCKS[k % 4], self.LATTICE_ORDERS[k // 4]): ms[k] for k in range(8)}
+        return (w.value, self.LATTICE_ORDERS[o.value]), table
 
     def save(self, path):
         self._check(load().lbm_save(self._ctx, str(path).encode()))

@@ -348,11 +348,38 @@ __device__ __forceinline__ void collide_shifted(const LBArgs &a, uint64_t n, int
     }
 }
 
-template <class L, int ST>
+// Workgroup -> tile (x stretch, row y, z).  Linear order: the tile is the
+// workgroup's own coordinates.  XCD order: the hardware deals workgroup ids
+// (x fastest) to its 8 XCDs in turn, id mod 8; the ids one XCD receives are
+// renumbered to one contiguous run of tiles, so that the stretches of a row
+// and the neighbouring rows share that XCD's L2.  The renumbering is a
+// bijection of [0, G) for any G (the first G mod 8 XCDs take one tile more);
+// the launcher uses it only for grids of fewer than 2^32 workgroups.
+template <bool XO>
+__device__ __forceinline__ void tile_of(uint32_t &xt, int &y, int &z) {
+    if (!XO) {
+        xt = blockIdx.x;
+        y = blockIdx.y;
+        z = blockIdx.z;
+        return;
+    }
+    const uint32_t gx = gridDim.x, G = gx * gridDim.y * gridDim.z;
+    const uint32_t b = blockIdx.x + gx * (blockIdx.y + gridDim.y * blockIdx.z);
+    const uint32_t k = b & 7u, q = G >> 3, r = G & 7u;
+    const uint32_t t = (k < r ? k * (q + 1) : r * (q + 1) + (k - r) * q) + (b >> 3);
+    const uint32_t row = t / gx;
+    xt = t - row * gx;
+    y = (int)(row % gridDim.y);
+    z = (int)(row / gridDim.y);
+}
+
+template <class L, int ST, bool XO>
 __global__ __launch_bounds__(256) void k_lb(LBArgs a) {
-    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    uint32_t xt;
+    int y, z;
+    tile_of<XO>(xt, y, z);
+    const int x = (int)xt * blockDim.x + threadIdx.x;
     if (x >= a.g.nx) return;
-    const int y = blockIdx.y, z = blockIdx.z;
     const uint64_t n = (uint64_t)x + (uint64_t)a.g.nx * ((uint64_t)y + (uint64_t)a.g.ny * (uint64_t)z);
     using T = typename Store<ST>::T;
     // the owner count is read before the populations, so a wavefront with a
@@ -482,7 +509,7 @@ static dim3 lattice_grid(const Geom &g, int &block) {
 }
 
 template <class L, int ST>
-static hipError_t lb_dispatch(const LBArgs &a, int width, hipStream_t s) {
+static hipError_t lb_dispatch(const LBArgs &a, int width, int order, hipStream_t s) {
     int block;
     dim3 grid = lattice_grid(a.g, block);
     if (width > 0) {
@@ -491,8 +518,17 @@ static hipError_t lb_dispatch(const LBArgs &a, int width, hipStream_t s) {
         block = width;
         grid.x = (unsigned)((a.g.nx + width - 1) / width);
     }
-    hipLaunchKernelGGL((k_lb<L, ST>), grid, dim3(block), 0, s, a);
+    const uint64_t groups = (uint64_t)grid.x * grid.y * grid.z;
+    if (order == 1 && groups < ((uint64_t)1 << 32))
+        hipLaunchKernelGGL((k_lb<L, ST, true>), grid, dim3(block), 0, s, a);
+    else
+        hipLaunchKernelGGL((k_lb<L, ST, false>), grid, dim3(block), 0, s, a);
     return hipGetLastError();
+}
+
+bool xcd_order_fits(const Geom &g, int width) {
+    const int w = lattice_block_width(g.nx, width);
+    return (uint64_t)((g.nx + w - 1) / w) * (uint64_t)g.ny * (uint64_t)g.nz < ((uint64_t)1 << 32);
 }
 
 int lattice_block_width(int nx, int width) {
@@ -504,15 +540,15 @@ int lattice_block_width(int nx, int width) {
     return block;
 }
 
-hipError_t launch_lb(int lattice, int storage, const LBArgs &a, int width, hipStream_t s) {
+hipError_t launch_lb(int lattice, int storage, const LBArgs &a, int width, int order, hipStream_t s) {
     if (lattice == 0) {
-        if (storage == 0) return lb_dispatch<D2Q9, 0>(a, width, s);
-        if (storage == 1) return lb_dispatch<D2Q9, 1>(a, width, s);
-        return lb_dispatch<D2Q9, 2>(a, width, s);
+        if (storage == 0) return lb_dispatch<D2Q9, 0>(a, width, order, s);
+        if (storage == 1) return lb_dispatch<D2Q9, 1>(a, width, order, s);
+        return lb_dispatch<D2Q9, 2>(a, width, order, s);
     }
-    if (storage == 0) return lb_dispatch<D3Q19, 0>(a, width, s);
-    if (storage == 1) return lb_dispatch<D3Q19, 1>(a, width, s);
-    return lb_dispatch<D3Q19, 2>(a, width, s);
+    if (storage == 0) return lb_dispatch<D3Q19, 0>(a, width, order, s);
+    if (storage == 1) return lb_dispatch<D3Q19, 1>(a, width, order, s);
+    return lb_dispatch<D3Q19, 2>(a, width, order, s);
 }
 
 #define LBIMB_DISPATCH(KERNEL, ...)                                                          \

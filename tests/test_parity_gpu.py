@@ -255,12 +255,15 @@ def test_graph_and_eager_agree_bitwise(gpu_lib):
 
 @pytest.mark.parametrize("storage", ["fp64", "fp32s", "fp16s"])
 def test_lattice_block_widths_bitwise(gpu_lib, storage):
-    """The lattice kernel's workgroup width changes the launch shape only:
+    """The lattice kernel's launch shape changes nothing but the launch:
     every width (the last workgroup of a row overhanging it by up to 170
-    threads) gives the state of the default launch bit for bit, in 3D with
-    walls and moving spheres and in 2D with rows wider than one workgroup."""
-    cases = [(3, (150, 40, 24), spheres((150, 40, 24), 4.0, 10, 51, 0.01)),
-             (2, (300, 48, 1), None)]
+    threads) in linear and in XCD order (grids of 1 x 39 x 23 up to
+    5 x 47 x 1 workgroups, counts of 1, 2, 3, 5 and 6 mod 8 among them, so
+    both branches of the renumbering run) gives the state of
+    the default launch bit for bit, in 3D with walls and moving spheres and in
+    2D with rows wider than one workgroup."""
+    cases = [(3, (150, 39, 23), spheres((150, 39, 23), 4.0, 10, 51, 0.01)),
+             (2, (300, 47, 1), None)]
     for dim, box, parts in cases:
         shape = box if dim == 3 else box[:2]
         say("lattice widths", storage, shape)
@@ -268,13 +271,14 @@ def test_lattice_block_widths_bitwise(gpu_lib, storage):
                   samples=4, kn=500.0, restitution=0.8, max_particles=10)
         f0 = seeded_f(dim, int(np.prod(shape)), 0.02, 7)
         ref = None
-        for width in (0, 64, 128, 192, 256):
+        for width, order in [(0, "linear")] + [(w, o) for o in ("linear", "xcd")
+                                               for w in (64, 128, 192, 256)]:
             s = gpu_lib.Simulation(dim, shape, 0.62, **kw)
             s.set_f(f0)
             if parts is not None:
                 s.set_particles(*parts)
-            s.set_lattice_block(width)
-            assert s.lattice_block == (width or (192 if box[0] == 150 else 256))
+            s.set_lattice_block(width, order)
+            assert s.lattice_block == (width or (192 if box[0] == 150 else 256), order)
             s.step(23)
             got = (s.get_f(), s.particles()[0] if parts is not None else None,
                    s.forces()[0] if parts is not None else None)
@@ -283,27 +287,28 @@ def test_lattice_block_widths_bitwise(gpu_lib, storage):
                 ref = got
                 continue
             for a, b in zip(got, ref):
-                assert a is None or np.array_equal(a, b), "width %d differs" % width
+                assert a is None or np.array_equal(a, b), "width %d %s differs" % (width, order)
 
 
-def test_lattice_block_width_fp64_parity(gpu_lib):
-    """A non-default width against the oracle directly (FP64 bar)."""
-    box = (150, 20, 12)
+@pytest.mark.parametrize("order", ["linear", "xcd"])
+def test_lattice_block_width_fp64_parity(gpu_lib, order):
+    """A non-default launch shape against the oracle directly (FP64 bar)."""
+    box = (150, 21, 13)
     parts = spheres(box, 3.0, 6, 61, 0.01)
-    say("width 64 vs oracle")
+    say("width 64 %s vs oracle" % order)
     orc, gpu = make_pair(gpu_lib, 3, box, 0.7, wall_y=True, fluid_force=(1e-6, 0, 0),
                          particle_accel=(0, -1e-5, 0), samples=4, kn=400.0, restitution=0.9,
                          particles=parts)
-    gpu.set_lattice_block(64)
+    gpu.set_lattice_block(64, order)
     orc.step(6)
     gpu.step(6)
-    assert_close(compare(orc, gpu), label="width 64 t=6")
+    assert_close(compare(orc, gpu), label="width 64 %s t=6" % order)
 
 
 def test_lattice_block_autotune(gpu_lib):
-    """The autotuner advances the state by 8 (steps + 1) real steps, keeps
-    one of the four widths, restores the timing mode with cleared counters,
-    and the tuned run continues bit for bit like an untuned one."""
+    """The autotuner advances the state by 16 (steps + 1) real steps, keeps
+    one of the eight launch shapes, restores the timing mode with cleared
+    counters, and the tuned run continues bit for bit like an untuned one."""
     box = (96, 30, 20)
     parts = spheres(box, 4.0, 5, 71, 0.01)
     say("lattice width autotune")
@@ -313,9 +318,10 @@ def test_lattice_block_autotune(gpu_lib):
     a.set_particles(*parts)
     a.set_timing(True, lattice_only=True)
     best, ms = a.autotune_lattice_block(steps=3)
-    assert a.t == 8 * 4
-    assert best in (64, 128, 192, 256) and a.lattice_block == best
-    assert sorted(ms) == [64, 128, 192, 256]
+    assert a.t == 16 * 4
+    assert best[0] in (64, 128, 192, 256) and best[1] in ("linear", "xcd")
+    assert a.lattice_block == best
+    assert len(ms) == 8 and best in ms
     assert all(math.isfinite(v) and v > 0 for v in ms.values())
     assert ms[best] == min(ms.values())
     t = a.get_timing()
@@ -326,11 +332,13 @@ def test_lattice_block_autotune(gpu_lib):
     a.step(6)
     b = gpu_lib.Simulation(3, box, 0.65, **kw)
     b.set_particles(*parts)
-    b.step(8 * 4 + 11)
+    b.step(16 * 4 + 11)
     assert np.array_equal(a.get_f(), b.get_f())
     assert np.array_equal(a.particles()[0], b.particles()[0])
     with pytest.raises(gpu_lib.LbmError):
         a.set_lattice_block(96)
+    with pytest.raises(ValueError):
+        a.set_lattice_block(64, "spiral")
     with pytest.raises(gpu_lib.LbmError):
         a.autotune_lattice_block(steps=0)
     assert a.lattice_block == best
