@@ -265,9 +265,10 @@ def main():
         "vs_baseline": None,
         "dtype": DTYPE["fp64"],
         "data": "synthetic (seeded random sphere placement, fluid at rest)",
-        "config": {"workload": "%s: D3Q19 %dx%dx%d, %s, %d spheres R=%g, tau %g, density ratio %g"
-                   % (w.name, *w.shape, "walls y" if w.wall_y else "periodic", w.count, w.radius,
-                      round(w.tau, 4), w.rho_ratio),
+        "config": {"workload": "%s: %s %s, %s, %d %s R=%g, tau %g, density ratio %g"
+                   % (w.name, "D3Q19" if w.dim == 3 else "D2Q9", "x".join(str(e) for e in w.shape),
+                      "walls y" if w.wall_y else "periodic", w.count,
+                      "spheres" if w.dim == 3 else "discs", w.radius, round(w.tau, 4), w.rho_ratio),
                    "nodes": w.nodes, "particles": w.count, "storage": "fp64", "eps": args.eps,
                    "lattice_block": base["lattice_block"],
                    "lattice_block_tuning_ms": base["lattice_block_tuning_ms"]},
