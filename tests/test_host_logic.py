@@ -41,3 +41,15 @@ def test_closure_neighbour_features():
     assert abs(X[0, E.NFEAT - 3] - 4 * 4.0 / 3.0 * math.pi * R ** 3 / L ** 3) < 1e-12
     assert abs(X[0, E.NFEAT - 1] - (4.0 - d) / d) < 1e-12
     assert np.allclose(scale, 3 * math.pi * nu * d * 0.02)
+
+
+def test_bench_launch_shape_option():
+    """bench.py --lattice-block: "auto", one shape for all, or per variant;
+    a shape is a width with an optional "/xcd" workgroup order, and the
+    text form round-trips."""
+    import bench
+    assert bench.parse_blocks("auto") == {}
+    assert bench.parse_blocks("192") == {v: (192, "linear") for v in ("fp64", "fp32s", "fp16s")}
+    assert bench.parse_blocks("fp64=256/xcd,fp32s=64") == {"fp64": (256, "xcd"), "fp32s": (64, "linear")}
+    for shape in ((64, "linear"), (256, "xcd")):
+        assert bench.parse_shape(bench.shape_text(shape)) == shape
