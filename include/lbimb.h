@@ -187,8 +187,9 @@ int lbm_get_timing(lbm_ctx *ctx, double *ms, int64_t *launches);
  * XCDs (which the hardware feeds workgroup ids in turn) takes one contiguous
  * run of tiles, keeping neighbouring rows in one L2.  The launch shape never
  * changes a bit of the result.  Takes effect from the next step (captured
- * step graphs are dropped).  Errors: LBM_E_INVALID for another width or
- * order, or for XCD order on a grid of 2^32 workgroups or more.
+ * step graphs are dropped).  A new context starts with width 0 and linear
+ * order.  Errors: LBM_E_INVALID for another width or order, or for XCD order
+ * on a grid of 2^32 workgroups or more.
  * lbm_get_lattice_block writes the width in use (the rule resolved) and the
  * order; LBM_E_INVALID for a null argument. */
 enum { LBM_ORDER_LINEAR = 0, LBM_ORDER_XCD = 1 };
