@@ -50,14 +50,22 @@ def measured_traffic(storage, workload, width):
 
 
 def parse_shape(text):
-    """"256" or "256/xcd" -> (256, "xcd")."""
-    w, _, order = text.partition("/")
-    return int(w), order or "linear"
+    """"256", "256/xcd", "192/cu3" or "256/xcd/cu4" -> (width, order, cu_groups)."""
+    parts = text.split("/")
+    order, cap = "linear", 0
+    for p in parts[1:]:
+        if p == "xcd":
+            order = "xcd"
+        elif p.startswith("cu"):
+            cap = int(p[2:])
+        else:
+            raise ValueError("bad launch shape %r" % text)
+    return int(parts[0]), order, cap
 
 
 def parse_blocks(spec):
     """--lattice-block: "auto", one launch shape for every variant, or per
-    variant ("fp64=192/xcd,fp32s=64")."""
+    variant ("fp64=256/xcd/cu3,fp32s=64")."""
     if spec == "auto":
         return {}
     if "=" not in spec:
@@ -66,7 +74,8 @@ def parse_blocks(spec):
 
 
 def shape_text(shape):
-    return "%d/%s" % shape if shape[1] != "linear" else "%d" % shape[0]
+    width, order, cap = shape
+    return "%d%s%s" % (width, "/xcd" if order == "xcd" else "", "/cu%d" % cap if cap else "")
 
 
 def run_variant(binding, inputs, w, parts, storage, steps, warmup, eps="sampling", block=None):
@@ -219,8 +228,8 @@ def main():
                     help="solid fraction by sub-cell sampling or by the paper's table lookup")
     ap.add_argument("--lattice-block", default="auto",
                     help='lattice kernel launch shape: "auto" (measured per variant), a width '
-                         '64/128/192/256 with an optional "/xcd" workgroup order, or per variant, '
-                         'e.g. "fp64=192/xcd,fp32s=64"')
+                         '64/128/192/256 with an optional "/xcd" workgroup order and "/cuN" cap of '
+                         'N workgroups per CU, or per variant, e.g. "fp64=256/xcd/cu3,fp32s=64"')
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the batched-ensemble and closure measurements")

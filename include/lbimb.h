@@ -185,32 +185,35 @@ int lbm_get_timing(lbm_ctx *ctx, double *ms, int64_t *launches);
  * masked).  order: LBM_ORDER_LINEAR hands tiles to workgroups in launch
  * order; LBM_ORDER_XCD renumbers workgroups so that each of the GPU's 8
  * XCDs (which the hardware feeds workgroup ids in turn) takes one contiguous
- * run of tiles, keeping neighbouring rows in one L2.  The launch shape never
- * changes a bit of the result.  Takes effect from the next step (captured
- * step graphs are dropped).  A new context starts with width 0 and linear
- * order.  Errors: LBM_E_INVALID for another width or order, or for XCD order
- * on a grid of 2^32 workgroups or more.
- * lbm_get_lattice_block writes the width in use (the rule resolved) and the
- * order; LBM_E_INVALID for a null argument. */
+ * run of tiles, keeping neighbouring rows in one L2.  cu_groups: 0, or at
+ * most 3..8 of the kernel's workgroups resident on one CU at a time (the
+ * launch reserves 160 KiB / cu_groups of LDS that the kernel does not use).
+ * The launch shape never changes a bit of the result.  Takes effect from the
+ * next step (captured step graphs are dropped).  A new context starts with
+ * width 0, linear order and no cap.  Errors: LBM_E_INVALID for another
+ * width, order or cap, or for XCD order on a grid of 2^32 workgroups or
+ * more.  lbm_get_lattice_block writes the width in use (the rule resolved),
+ * the order and the cap; LBM_E_INVALID for a null argument. */
 enum { LBM_ORDER_LINEAR = 0, LBM_ORDER_XCD = 1 };
-int lbm_set_lattice_block(lbm_ctx *ctx, int threads, int order);
-int lbm_get_lattice_block(const lbm_ctx *ctx, int *threads, int *order);
+int lbm_set_lattice_block(lbm_ctx *ctx, int threads, int order, int cu_groups);
+int lbm_get_lattice_block(const lbm_ctx *ctx, int *threads, int *order, int *cu_groups);
 
-/* Chooses the lattice kernel's launch shape by measurement.  Each of the 8
- * candidates (order k / 4, width 64, 128, 192, 256 for k % 4 = 0..3; XCD
- * candidates skipped where the grid is too large for them) runs 1 + `steps`
- * real time steps twice, so the simulation advances by up to 16 (1 + steps)
- * steps; the result does not depend on the shape.  The lattice phase is
- * timed as in timing mode 2, and the candidate with the shortest mean
- * lattice kernel time is kept.  best_threads and best_order (may be null)
- * receive it; ms_out (8 doubles, may be null) the mean milliseconds per
+/* Chooses the lattice kernel's launch shape by measurement.  Each of the 24
+ * candidates (width 64, 128, 192, 256 for k % 4 = 0..3, order (k / 4) % 2,
+ * cap 0, 4, 3 workgroups per CU for k / 8 = 0..2; XCD candidates skipped
+ * where the grid is too large for them) runs 1 + `steps` real time steps
+ * twice, so the simulation advances by up to 48 (1 + steps) steps; the result
+ * does not depend on the shape.  The lattice phase is timed as in timing
+ * mode 2, and the candidate with the shortest mean lattice kernel time is
+ * kept.  best_threads, best_order and best_cu_groups (each may be null)
+ * receive it; ms_out (24 doubles, may be null) the mean milliseconds per
  * lattice launch of each candidate (the faster of the two passes; HUGE_VAL
  * for a skipped one).  The timing mode in force before the call is restored
  * with its counters cleared.  Errors: LBM_E_INVALID for steps outside
  * 1..100000; a failed step returns its code with the previous shape and
  * timing mode restored. */
 int lbm_autotune_lattice_block(lbm_ctx *ctx, int steps, int *best_threads, int *best_order,
-                               double *ms_out);
+                               int *best_cu_groups, double *ms_out);
 
 /* Writes / reads the full state (populations in storage format, particles,
  * forces, time) to / from a file.  The file records the configuration; a

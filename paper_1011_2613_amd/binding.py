@@ -87,9 +87,10 @@ def load():
     L.lbm_particle_count.restype = i64
     L.lbm_set_timing.argtypes = [vp, C.c_int]
     L.lbm_get_timing.argtypes = [vp, dp, C.POINTER(i64)]
-    L.lbm_set_lattice_block.argtypes = [vp, C.c_int, C.c_int]
-    L.lbm_get_lattice_block.argtypes = [vp, C.POINTER(C.c_int), C.POINTER(C.c_int)]
-    L.lbm_autotune_lattice_block.argtypes = [vp, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int), dp]
+    ip = C.POINTER(C.c_int)
+    L.lbm_set_lattice_block.argtypes = [vp, C.c_int, C.c_int, C.c_int]
+    L.lbm_get_lattice_block.argtypes = [vp, ip, ip, ip]
+    L.lbm_autotune_lattice_block.argtypes = [vp, C.c_int, ip, ip, ip, dp]
     L.lbm_save.argtypes = [vp, C.c_char_p]
     L.lbm_load.argtypes = [vp, C.c_char_p]
     L.lbm_error_string.argtypes = [C.c_int]
@@ -274,30 +275,34 @@ class Simulation:
 
     LATTICE_BLOCKS = (64, 128, 192, 256)
     LATTICE_ORDERS = ("linear", "xcd")
+    LATTICE_CAPS = (0, 4, 3)
 
-    def set_lattice_block(self, threads, order="linear"):
+    def set_lattice_block(self, threads, order="linear", cu_groups=0):
         """Launch shape of the lattice kernel: workgroup width (0: built-in
-        rule) and workgroup order ("linear" or "xcd")."""
+        rule), workgroup order ("linear" or "xcd") and the most workgroups
+        resident on one CU (0: no cap, else 3..8)."""
         self._check(load().lbm_set_lattice_block(self._ctx, int(threads),
-                                                 self.LATTICE_ORDERS.index(order)))
+                                                 self.LATTICE_ORDERS.index(order), int(cu_groups)))
 
     @property
     def lattice_block(self):
-        """(width, order) of the lattice kernel's launches."""
-        w, o = C.c_int(0), C.c_int(0)
-        self._check(load().lbm_get_lattice_block(self._ctx, C.byref(w), C.byref(o)))
-        return w.value, self.LATTICE_ORDERS[o.value]
+        """(width, order, cu_groups) of the lattice kernel's launches."""
+        w, o, g = C.c_int(0), C.c_int(0), C.c_int(0)
+        self._check(load().lbm_get_lattice_block(self._ctx, C.byref(w), C.byref(o), C.byref(g)))
+        return w.value, self.LATTICE_ORDERS[o.value], g.value
 
     def autotune_lattice_block(self, steps=20):
-        """Time the lattice kernel at each width and order over real steps
-        (the state advances by up to 16 (steps + 1) steps) and keep the
-        fastest.  Returns ((width, order), {(width, order): mean ms per
-        lattice launch})."""
-        w, o = C.c_int(0), C.c_int(0)
-        ms = (C.c_double * 8)()
-        self._check(load().lbm_autotune_lattice_block(self._ctx, int(steps), C.byref(w), C.byref(o), ms))
-        table = {(self.LATTICE_BLOCKS[k % 4], self.LATTICE_ORDERS[k // 4]): ms[k] for k in range(8)}
-        return (w.value, self.LATTICE_ORDERS[o.value]), table
+        """Time the lattice kernel at each launch shape over real steps (the
+        state advances by up to 48 (steps + 1) steps) and keep the fastest.
+        Returns ((width, order, cu_groups), {shape: mean ms per lattice
+        launch})."""
+        w, o, g = C.c_int(0), C.c_int(0), C.c_int(0)
+        ms = (C.c_double * 24)()
+        self._check(load().lbm_autotune_lattice_block(self._ctx, int(steps), C.byref(w), C.byref(o),
+                                                      C.byref(g), ms))
+        table = {(self.LATTICE_BLOCKS[k % 4], self.LATTICE_ORDERS[(k // 4) % 2],
+                  self.LATTICE_CAPS[k // 8]): ms[k] for k in range(24)}
+        return (w.value, self.LATTICE_ORDERS[o.value], g.value), table
 
     def save(self, path):
         self._check(load().lbm_save(self._ctx, str(path).encode()))

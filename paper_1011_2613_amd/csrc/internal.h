@@ -209,8 +209,11 @@ int batch_persistent_grid();
 // launchers (lb_kernels.hip)
 // width: threads per workgroup of the lattice kernel (64, 128, 192 or 256),
 // 0 for the built-in rule (the whole row up to 256 threads); order: 0 linear,
-// 1 XCD order (workgroups renumbered so each XCD takes a contiguous run)
-hipError_t launch_lb(int lattice, int storage, const LBArgs &a, int width, int order, hipStream_t s);
+// 1 XCD order (workgroups renumbered so each XCD takes a contiguous run);
+// cu_groups: 0, or 3..8 workgroups per CU at most (an unused LDS reservation)
+hipError_t launch_lb(int lattice, int storage, const LBArgs &a, int width, int order, int cu_groups,
+                     hipStream_t s);
+unsigned lds_reserve_bytes(int cu_groups);
 int lattice_block_width(int nx, int width);        // the width a launch uses
 bool xcd_order_fits(const Geom &g, int width);     // grid below 2^32 workgroups
 hipError_t launch_fill_rest_f64(int lattice, const Geom &g, double *A, hipStream_t s);

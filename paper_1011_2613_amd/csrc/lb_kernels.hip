@@ -509,7 +509,7 @@ static dim3 lattice_grid(const Geom &g, int &block) {
 }
 
 template <class L, int ST>
-static hipError_t lb_dispatch(const LBArgs &a, int width, int order, hipStream_t s) {
+static hipError_t lb_dispatch(const LBArgs &a, int width, int order, int cu_groups, hipStream_t s) {
     int block;
     dim3 grid = lattice_grid(a.g, block);
     if (width > 0) {
@@ -519,11 +519,20 @@ static hipError_t lb_dispatch(const LBArgs &a, int width, int order, hipStream_t
         grid.x = (unsigned)((a.g.nx + width - 1) / width);
     }
     const uint64_t groups = (uint64_t)grid.x * grid.y * grid.z;
+    const unsigned lds = lds_reserve_bytes(cu_groups);
     if (order == 1 && groups < ((uint64_t)1 << 32))
-        hipLaunchKernelGGL((k_lb<L, ST, true>), grid, dim3(block), 0, s, a);
+        hipLaunchKernelGGL((k_lb<L, ST, true>), grid, dim3(block), lds, s, a);
     else
-        hipLaunchKernelGGL((k_lb<L, ST, false>), grid, dim3(block), 0, s, a);
+        hipLaunchKernelGGL((k_lb<L, ST, false>), grid, dim3(block), lds, s, a);
     return hipGetLastError();
+}
+
+// The lattice kernel uses no LDS.  Reserving an unused share of a CU's 160 KiB
+// caps how many of its workgroups a CU holds at once (cu_groups, 3..8), below
+// what its registers allow; 0 reserves nothing.
+unsigned lds_reserve_bytes(int cu_groups) {
+    if (cu_groups <= 0) return 0;
+    return (unsigned)(163840 / cu_groups) / 512u * 512u;
 }
 
 bool xcd_order_fits(const Geom &g, int width) {
@@ -540,15 +549,16 @@ int lattice_block_width(int nx, int width) {
     return block;
 }
 
-hipError_t launch_lb(int lattice, int storage, const LBArgs &a, int width, int order, hipStream_t s) {
+hipError_t launch_lb(int lattice, int storage, const LBArgs &a, int width, int order, int cu_groups,
+                     hipStream_t s) {
     if (lattice == 0) {
-        if (storage == 0) return lb_dispatch<D2Q9, 0>(a, width, order, s);
-        if (storage == 1) return lb_dispatch<D2Q9, 1>(a, width, order, s);
-        return lb_dispatch<D2Q9, 2>(a, width, order, s);
+        if (storage == 0) return lb_dispatch<D2Q9, 0>(a, width, order, cu_groups, s);
+        if (storage == 1) return lb_dispatch<D2Q9, 1>(a, width, order, cu_groups, s);
+        return lb_dispatch<D2Q9, 2>(a, width, order, cu_groups, s);
     }
-    if (storage == 0) return lb_dispatch<D3Q19, 0>(a, width, order, s);
-    if (storage == 1) return lb_dispatch<D3Q19, 1>(a, width, order, s);
-    return lb_dispatch<D3Q19, 2>(a, width, order, s);
+    if (storage == 0) return lb_dispatch<D3Q19, 0>(a, width, order, cu_groups, s);
+    if (storage == 1) return lb_dispatch<D3Q19, 1>(a, width, order, cu_groups, s);
+    return lb_dispatch<D3Q19, 2>(a, width, order, cu_groups, s);
 }
 
 #define LBIMB_DISPATCH(KERNEL, ...)                                                          \

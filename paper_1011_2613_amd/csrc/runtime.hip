@@ -141,6 +141,7 @@ struct lbm_ctx {
     int timing;  // 0 off, 1 every phase, 2 the lattice phase only
     int lb_width;  // lattice kernel workgroup width, 0 for the built-in rule
     int lb_order;  // lattice kernel workgroup order, LBM_ORDER_LINEAR / _XCD
+    int lb_cu_groups;  // lattice kernel workgroups per CU at most, 0: no cap
     bool rec_open;
     std::vector<TimedEvent> events;
     size_t ev_used;
@@ -351,7 +352,7 @@ hipError_t enqueue_step(lbm_ctx *c, int from, hipStream_t s, int slot) {
         phase_end(c, s);
     }
     phase_begin(c, 1, s);
-    if ((e = launch_lb(lattice, storage, lb_args(c, from), c->lb_width, c->lb_order, s)) != hipSuccess) return e;
+    if ((e = launch_lb(lattice, storage, lb_args(c, from), c->lb_width, c->lb_order, c->lb_cu_groups, s)) != hipSuccess) return e;
     phase_end(c, s);
     if (c->np > 0) {
         ForceArgs fo;
@@ -504,6 +505,7 @@ int lbm_create(const lbm_config *cfg, void *workspace, size_t ws_bytes, void *hi
     c->timing = 0;
     c->lb_width = 0;
     c->lb_order = LBM_ORDER_LINEAR;
+    c->lb_cu_groups = 0;
     c->rec_open = false;
     c->ev_used = 0;
     for (int k = 0; k < LBM_NPHASES; k++) { c->phase_ms[k] = 0.0; c->phase_n[k] = 0; }
@@ -898,7 +900,7 @@ int lbm_get_timing(lbm_ctx *c, double *ms, int64_t *launches) {
     return LBM_OK;
 }
 
-int lbm_set_lattice_block(lbm_ctx *c, int threads, int order) {
+int lbm_set_lattice_block(lbm_ctx *c, int threads, int order, int cu_groups) {
     if (!c) return LBM_E_INVALID;
     if (!(threads == 0 || threads == 64 || threads == 128 || threads == 192 || threads == 256))
         return fail(c, LBM_E_INVALID, "lattice block width %d is not 0, 64, 128, 192 or 256", threads);
@@ -906,19 +908,23 @@ int lbm_set_lattice_block(lbm_ctx *c, int threads, int order) {
         return fail(c, LBM_E_INVALID, "unknown lattice block order %d", order);
     if (order == LBM_ORDER_XCD && !xcd_order_fits(c->g, threads))
         return fail(c, LBM_E_INVALID, "XCD order needs fewer than 2^32 workgroups");
+    if (!(cu_groups == 0 || (cu_groups >= 3 && cu_groups <= 8)))
+        return fail(c, LBM_E_INVALID, "workgroups per CU %d is not 0 or 3..8", cu_groups);
     HIPCHK(c, hipStreamSynchronize(c->stream));
-    if (threads != c->lb_width || order != c->lb_order) {
+    if (threads != c->lb_width || order != c->lb_order || cu_groups != c->lb_cu_groups) {
         c->lb_width = threads;
         c->lb_order = order;
+        c->lb_cu_groups = cu_groups;
         drop_graphs(c);  // captured steps hold the old launch shape
     }
     return LBM_OK;
 }
 
-int lbm_get_lattice_block(const lbm_ctx *c, int *threads, int *order) {
-    if (!c || !threads || !order) return LBM_E_INVALID;
+int lbm_get_lattice_block(const lbm_ctx *c, int *threads, int *order, int *cu_groups) {
+    if (!c || !threads || !order || !cu_groups) return LBM_E_INVALID;
     *threads = lattice_block_width(c->cfg.nx, c->lb_width);
     *order = c->lb_order;
+    *cu_groups = c->lb_cu_groups;
     return LBM_OK;
 }
 
@@ -927,20 +933,23 @@ int lbm_get_lattice_block(const lbm_ctx *c, int *threads, int *order) {
 // twice in opposite orders so that a drift of the clock or of the state
 // between the first and the last candidate does not favour one of them.
 int lbm_autotune_lattice_block(lbm_ctx *c, int steps, int *best_threads, int *best_order,
-                               double *ms_out) {
+                               int *best_cu_groups, double *ms_out) {
     if (!c || steps < 1 || steps > 100000) return LBM_E_INVALID;
     static const int widths[4] = {64, 128, 192, 256};
-    constexpr int NC = 8;  // candidate k: order k / 4, width widths[k % 4]
-    const int prev_timing = c->timing, prev_width = c->lb_width, prev_order = c->lb_order;
+    static const int caps[3] = {0, 4, 3};
+    // candidate k: width widths[k % 4], order (k / 4) % 2, cap caps[k / 8]
+    constexpr int NC = 24;
+    const int prev_timing = c->timing, prev_width = c->lb_width, prev_order = c->lb_order,
+              prev_cap = c->lb_cu_groups;
     double best_ms[NC];
     for (int k = 0; k < NC; k++) best_ms[k] = HUGE_VAL;
     int r = LBM_OK;
     for (int pass = 0; pass < 2 && r == LBM_OK; pass++) {
         for (int j = 0; j < NC && r == LBM_OK; j++) {
             const int k = pass == 0 ? j : NC - 1 - j;
-            const int order = k / 4, width = widths[k % 4];
+            const int order = (k / 4) % 2, width = widths[k % 4], cap = caps[k / 8];
             if (order == LBM_ORDER_XCD && !xcd_order_fits(c->g, width)) continue;
-            if ((r = lbm_set_lattice_block(c, width, order)) != LBM_OK) break;
+            if ((r = lbm_set_lattice_block(c, width, order, cap)) != LBM_OK) break;
             if ((r = lbm_set_timing(c, 2)) != LBM_OK) break;
             if ((r = lbm_step(c, 1)) != LBM_OK) break;  // first launch of this shape, untimed
             if ((r = lbm_set_timing(c, 2)) != LBM_OK) break;
@@ -954,7 +963,7 @@ int lbm_autotune_lattice_block(lbm_ctx *c, int steps, int *best_threads, int *be
     if (r != LBM_OK) {
         char msg[512];
         memcpy(msg, c->err, sizeof(msg));
-        (void)lbm_set_lattice_block(c, prev_width, prev_order);
+        (void)lbm_set_lattice_block(c, prev_width, prev_order, prev_cap);
         (void)lbm_set_timing(c, prev_timing);
         memcpy(c->err, msg, sizeof(msg));
         memcpy(g_err, msg, sizeof(g_err));
@@ -963,11 +972,12 @@ int lbm_autotune_lattice_block(lbm_ctx *c, int steps, int *best_threads, int *be
     int best = 0;
     for (int k = 1; k < NC; k++)
         if (best_ms[k] < best_ms[best]) best = k;
-    r = lbm_set_lattice_block(c, widths[best % 4], best / 4);
+    r = lbm_set_lattice_block(c, widths[best % 4], (best / 4) % 2, caps[best / 8]);
     if (r == LBM_OK) r = lbm_set_timing(c, prev_timing);
     if (r != LBM_OK) return r;
     if (best_threads) *best_threads = widths[best % 4];
-    if (best_order) *best_order = best / 4;
+    if (best_order) *best_order = (best / 4) % 2;
+    if (best_cu_groups) *best_cu_groups = caps[best / 8];
     if (ms_out)
         for (int k = 0; k < NC; k++) ms_out[k] = best_ms[k];
     return LBM_OK;

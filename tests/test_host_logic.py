@@ -45,11 +45,12 @@ def test_closure_neighbour_features():
 
 def test_bench_launch_shape_option():
     """bench.py --lattice-block: "auto", one shape for all, or per variant;
-    a shape is a width with an optional "/xcd" workgroup order, and the
-    text form round-trips."""
+    a shape is a width with an optional "/xcd" workgroup order and "/cuN"
+    cap, and the text form round-trips."""
     import bench
     assert bench.parse_blocks("auto") == {}
-    assert bench.parse_blocks("192") == {v: (192, "linear") for v in ("fp64", "fp32s", "fp16s")}
-    assert bench.parse_blocks("fp64=256/xcd,fp32s=64") == {"fp64": (256, "xcd"), "fp32s": (64, "linear")}
-    for shape in ((64, "linear"), (256, "xcd")):
+    assert bench.parse_blocks("192") == {v: (192, "linear", 0) for v in ("fp64", "fp32s", "fp16s")}
+    assert bench.parse_blocks("fp64=256/xcd/cu3,fp32s=64") == {"fp64": (256, "xcd", 3),
+                                                             "fp32s": (64, "linear", 0)}
+    for shape in ((64, "linear", 0), (256, "xcd", 0), (192, "linear", 4), (256, "xcd", 3)):
         assert bench.parse_shape(bench.shape_text(shape)) == shape

@@ -257,7 +257,7 @@ def test_graph_and_eager_agree_bitwise(gpu_lib):
 def test_lattice_block_widths_bitwise(gpu_lib, storage):
     """The lattice kernel's launch shape changes nothing but the launch:
     every width (the last workgroup of a row overhanging it by up to 170
-    threads) in linear and in XCD order (grids of 1 x 39 x 23 up to
+    threads) in linear and in XCD order, and with caps of workgroups per CU, (grids of 1 x 39 x 23 up to
     5 x 47 x 1 workgroups, counts of 1, 2, 3, 5 and 6 mod 8 among them, so
     both branches of the renumbering run) gives the state of
     the default launch bit for bit, in 3D with walls and moving spheres and in
@@ -271,14 +271,15 @@ def test_lattice_block_widths_bitwise(gpu_lib, storage):
                   samples=4, kn=500.0, restitution=0.8, max_particles=10)
         f0 = seeded_f(dim, int(np.prod(shape)), 0.02, 7)
         ref = None
-        for width, order in [(0, "linear")] + [(w, o) for o in ("linear", "xcd")
-                                               for w in (64, 128, 192, 256)]:
+        shapes = [(0, "linear", 0)] + [(w, o, 0) for o in ("linear", "xcd") for w in (64, 128, 192, 256)]
+        shapes += [(64, "linear", 3), (256, "xcd", 4), (192, "xcd", 8)]
+        for width, order, cap in shapes:
             s = gpu_lib.Simulation(dim, shape, 0.62, **kw)
             s.set_f(f0)
             if parts is not None:
                 s.set_particles(*parts)
-            s.set_lattice_block(width, order)
-            assert s.lattice_block == (width or (192 if box[0] == 150 else 256), order)
+            s.set_lattice_block(width, order, cap)
+            assert s.lattice_block == (width or (192 if box[0] == 150 else 256), order, cap)
             s.step(23)
             got = (s.get_f(), s.particles()[0] if parts is not None else None,
                    s.forces()[0] if parts is not None else None)
@@ -287,7 +288,7 @@ def test_lattice_block_widths_bitwise(gpu_lib, storage):
                 ref = got
                 continue
             for a, b in zip(got, ref):
-                assert a is None or np.array_equal(a, b), "width %d %s differs" % (width, order)
+                assert a is None or np.array_equal(a, b), "shape %d %s %d differs" % (width, order, cap)
 
 
 @pytest.mark.parametrize("order", ["linear", "xcd"])
@@ -299,15 +300,15 @@ def test_lattice_block_width_fp64_parity(gpu_lib, order):
     orc, gpu = make_pair(gpu_lib, 3, box, 0.7, wall_y=True, fluid_force=(1e-6, 0, 0),
                          particle_accel=(0, -1e-5, 0), samples=4, kn=400.0, restitution=0.9,
                          particles=parts)
-    gpu.set_lattice_block(64, order)
+    gpu.set_lattice_block(64, order, 3)
     orc.step(6)
     gpu.step(6)
     assert_close(compare(orc, gpu), label="width 64 %s t=6" % order)
 
 
 def test_lattice_block_autotune(gpu_lib):
-    """The autotuner advances the state by 16 (steps + 1) real steps, keeps
-    one of the eight launch shapes, restores the timing mode with cleared
+    """The autotuner advances the state by 48 (steps + 1) real steps, keeps
+    one of the 24 launch shapes, restores the timing mode with cleared
     counters, and the tuned run continues bit for bit like an untuned one."""
     box = (96, 30, 20)
     parts = spheres(box, 4.0, 5, 71, 0.01)
@@ -318,10 +319,10 @@ def test_lattice_block_autotune(gpu_lib):
     a.set_particles(*parts)
     a.set_timing(True, lattice_only=True)
     best, ms = a.autotune_lattice_block(steps=3)
-    assert a.t == 16 * 4
-    assert best[0] in (64, 128, 192, 256) and best[1] in ("linear", "xcd")
+    assert a.t == 48 * 4
+    assert best[0] in (64, 128, 192, 256) and best[1] in ("linear", "xcd") and best[2] in (0, 4, 3)
     assert a.lattice_block == best
-    assert len(ms) == 8 and best in ms
+    assert len(ms) == 24 and best in ms
     assert all(math.isfinite(v) and v > 0 for v in ms.values())
     assert ms[best] == min(ms.values())
     t = a.get_timing()
@@ -332,13 +333,16 @@ def test_lattice_block_autotune(gpu_lib):
     a.step(6)
     b = gpu_lib.Simulation(3, box, 0.65, **kw)
     b.set_particles(*parts)
-    b.step(16 * 4 + 11)
+    b.step(48 * 4 + 11)
     assert np.array_equal(a.get_f(), b.get_f())
     assert np.array_equal(a.particles()[0], b.particles()[0])
     with pytest.raises(gpu_lib.LbmError):
         a.set_lattice_block(96)
     with pytest.raises(ValueError):
         a.set_lattice_block(64, "spiral")
+    for cap in (1, 2, 9):
+        with pytest.raises(gpu_lib.LbmError):
+            a.set_lattice_block(64, "linear", cap)
     with pytest.raises(gpu_lib.LbmError):
         a.autotune_lattice_block(steps=0)
     assert a.lattice_block == best
