@@ -34,19 +34,19 @@ def kernel_source_sha():
 def measured_traffic(storage, workload, width):
     """HBM bytes per launch of the lattice kernel from the committed rocprofv3
     counter runs, if they were taken on the current kernel source at the
-    workgroup width in use."""
+    launch shape in use (a record, or a list of records for several shapes)."""
     path = os.path.join(ROOT, "profiles", "lb_kernel_traffic.json")
     try:
         with open(path) as f:
             d = json.load(f)
     except (OSError, ValueError):
         return None
-    rec = d.get("%s_%s" % (workload, storage))
-    if not rec or rec.get("kernel_source_sha") != kernel_source_sha():
-        return None
-    if rec.get("lattice_block") != width:
-        return None
-    return rec.get("bytes_per_launch")
+    recs = d.get("%s_%s" % (workload, storage))
+    for rec in recs if isinstance(recs, list) else [recs]:
+        if (rec and rec.get("kernel_source_sha") == kernel_source_sha()
+                and rec.get("lattice_block") == width):
+            return rec.get("bytes_per_launch")
+    return None
 
 
 def parse_shape(text):

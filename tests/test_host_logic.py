@@ -54,3 +54,24 @@ def test_bench_launch_shape_option():
                                                              "fp32s": (64, "linear", 0)}
     for shape in ((64, "linear", 0), (256, "xcd", 0), (192, "linear", 4), (256, "xcd", 3)):
         assert bench.parse_shape(bench.shape_text(shape)) == shape
+
+
+def test_bench_traffic_lookup_by_shape(tmp_path, monkeypatch):
+    """The committed counter records are matched on kernel source and launch
+    shape; a storage mode may carry one record or a list of them."""
+    import json
+    import bench
+    (tmp_path / "profiles").mkdir()
+    recs = {"C3_fp64": [{"kernel_source_sha": "s1", "lattice_block": "256/xcd/cu4", "bytes_per_launch": 11},
+                        {"kernel_source_sha": "s1", "lattice_block": "192/xcd/cu4", "bytes_per_launch": 12}],
+            "C3_fp32s": {"kernel_source_sha": "s1", "lattice_block": "64", "bytes_per_launch": 21}}
+    (tmp_path / "profiles" / "lb_kernel_traffic.json").write_text(json.dumps(recs))
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    monkeypatch.setattr(bench, "kernel_source_sha", lambda: "s1")
+    assert bench.measured_traffic("fp64", "C3", "192/xcd/cu4") == 12
+    assert bench.measured_traffic("fp64", "C3", "256/xcd/cu4") == 11
+    assert bench.measured_traffic("fp64", "C3", "256") is None
+    assert bench.measured_traffic("fp32s", "C3", "64") == 21
+    assert bench.measured_traffic("fp16s", "C3", "64") is None
+    monkeypatch.setattr(bench, "kernel_source_sha", lambda: "s2")
+    assert bench.measured_traffic("fp32s", "C3", "64") is None
