@@ -187,7 +187,8 @@ int lbm_get_timing(lbm_ctx *ctx, double *ms, int64_t *launches);
  * XCDs (which the hardware feeds workgroup ids in turn) takes one contiguous
  * run of tiles, keeping neighbouring rows in one L2.  cu_groups: 0, or at
  * most 3..8 of the kernel's workgroups resident on one CU at a time (the
- * launch reserves 160 KiB / cu_groups of LDS that the kernel does not use).
+ * launch reserves 160 KiB / cu_groups of LDS, rounded down to 512 bytes,
+ * that the kernel does not use).
  * The launch shape never changes a bit of the result.  Takes effect from the
  * next step (captured step graphs are dropped).  A new context starts with
  * width 0, linear order and no cap.  Errors: LBM_E_INVALID for another
