@@ -2,6 +2,8 @@
 
 The oracle is compiled with gcc, strict IEEE binary64 semantics: no fast-math,
 no floating-point contraction, so every expression rounds exactly as written.
+OpenMP splits its per-node and per-particle loops over threads without
+changing any result (orc_set_threads(1) gives the serial program).
 """
 import os
 import subprocess
@@ -12,7 +14,7 @@ SRC = os.path.join(HERE, "lbimb_oracle.c")
 LIB = os.path.join(HERE, "liblbimb_oracle.so")
 
 CFLAGS = ["-O2", "-std=c99", "-fno-fast-math", "-ffp-contract=off",
-          "-fno-math-errno", "-fPIC", "-shared", "-Wall", "-Wextra"]
+          "-fno-math-errno", "-fopenmp", "-fPIC", "-shared", "-Wall", "-Wextra"]
 
 
 def build(verbose=False):

@@ -47,8 +47,20 @@
  * Floating point: IEEE binary64, round to nearest even, compiled with
  * -ffp-contract=off and no fast-math.  Every expression is evaluated left to
  * right exactly as written.
+ *
+ * Threads (OpenMP, optional): the per-node loops (footprint, collision,
+ * streaming, moments) and the per-particle loops (force sums, contacts,
+ * integration) are split over threads without changing any result.  Every
+ * node and every particle is still computed by exactly the same arithmetic
+ * in the same order; in particular the footprint gives each thread a slab of
+ * the outermost lattice axis and every thread walks the particles in
+ * ascending id, so each node still accumulates its owners in ascending id.
+ * orc_set_threads(1) gives the plain serial program.
  */
 #include <math.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -358,6 +370,7 @@ orc_sim *orc_create(int dim, int nx, int ny, int nz, int wall_y, double tau,
     double u0[3] = {0.0, 0.0, 0.0};
     for (int i = 0; i < s->L.Q; i++) {
         double fe = feq_i(&s->L, i, 1.0, u0);
+#pragma omp parallel for schedule(static)
         for (long n = 0; n < s->N; n++) s->f[(long)i * s->N + n] = fe;
     }
     return s;
@@ -454,6 +467,7 @@ int orc_get_f(const orc_sim *s, double *f) {
 /* Moments of the pre-collision f(x,t): rho[N], u[D][N] = sum_i f_i c_i / rho. */
 int orc_get_macro(const orc_sim *s, double *rho, double *u) {
     const orc_lattice *L = &s->L;
+#pragma omp parallel for schedule(static)
     for (long n = 0; n < s->N; n++) {
         double r = 0.0, j[3] = {0.0, 0.0, 0.0};
         for (int i = 0; i < L->Q; i++) {
@@ -496,21 +510,23 @@ long orc_time(const orc_sim *s) { return s->t; }
 /* ------------------------------------------------------------ step pieces */
 
 /* Footprint: total count per node and the count-weighted rigid velocity sum,
- * accumulated over particles in ascending id. */
-static void footprint(orc_sim *s) {
-    memset(s->ctot, 0, sizeof(int) * (size_t)s->N);
-    memset(s->vnum, 0, sizeof(double) * 3 * (size_t)s->N);
+ * accumulated over particles in ascending id.  This pass covers the nodes
+ * whose outermost coordinate (z in 3D, y in 2D) lies in [o0, o1); nodes
+ * beyond a wall do not exist. */
+static void footprint_slab(orc_sim *s, int o0, int o1) {
     const int D = s->L.D;
     for (int p = 0; p < s->np; p++) {
         int lo[3], hi[3];
         particle_bbox(s, p, lo, hi);
         const double *xp = &s->x[3 * p], *vp = &s->v[3 * p], *wp = &s->om[3 * p];
-        for (int cz = lo[2]; cz <= hi[2]; cz++)
-            for (int cy = lo[1]; cy <= hi[1]; cy++)
+        for (int cz = lo[2]; cz <= hi[2]; cz++) {
+            int iz = D == 3 ? wrap_coord(s, 2, cz) : 0;
+            if (iz < 0 || (D == 3 && (iz < o0 || iz >= o1))) continue;
+            for (int cy = lo[1]; cy <= hi[1]; cy++) {
+                int iy = wrap_coord(s, 1, cy);
+                if (iy < 0 || (D == 2 && (iy < o0 || iy >= o1))) continue;
                 for (int cx = lo[0]; cx <= hi[0]; cx++) {
-                    int ix = wrap_coord(s, 0, cx), iy = wrap_coord(s, 1, cy);
-                    int iz = D == 3 ? wrap_coord(s, 2, cz) : 0;
-                    if (ix < 0 || iy < 0 || iz < 0) continue;
+                    int ix = wrap_coord(s, 0, cx);
                     int cnt = node_count(s, p, ix, iy, iz);
                     if (cnt == 0) continue;
                     long n = node_index(s, ix, iy, iz);
@@ -532,7 +548,26 @@ static void footprint(orc_sim *s) {
                         s->vnum[(long)a * s->N + n] = s->vnum[(long)a * s->N + n] + c * vr[a];
                     s->ctot[n] += cnt;
                 }
+            }
+        }
     }
+}
+
+static void footprint(orc_sim *s) {
+    const long N = s->N;
+#pragma omp parallel for schedule(static)
+    for (long n = 0; n < N; n++) {
+        s->ctot[n] = 0;
+        s->vnum[n] = 0.0;
+        s->vnum[N + n] = 0.0;
+        s->vnum[2 * N + n] = 0.0;
+    }
+    /* slabs of the outermost axis are disjoint node sets */
+    const int nouter = s->L.D == 3 ? s->nz : s->ny;
+    const int nslab = nouter < 64 ? nouter : 64;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int k = 0; k < nslab; k++)
+        footprint_slab(s, (int)((long)nouter * k / nslab), (int)((long)nouter * (k + 1) / nslab));
 }
 
 /* Collision of one node, Eq. (1).  fin[Q] are the pre-collision values,
@@ -597,6 +632,7 @@ static void collide_all(orc_sim *s) {
     const orc_lattice *L = &s->L;
     const int Q = L->Q;
     const int Smax = L->D == 2 ? s->S * s->S : s->S * s->S * s->S;
+#pragma omp parallel for schedule(static)
     for (long n = 0; n < s->N; n++) {
         double fin[19], fout[19], vs[3] = {0.0, 0.0, 0.0}, q[3];
         for (int i = 0; i < Q; i++) fin[i] = s->f[(long)i * s->N + n];
@@ -615,6 +651,8 @@ static void collide_all(orc_sim *s) {
  * reflected into the opposite direction at the same node. */
 static void stream_all(orc_sim *s) {
     const orc_lattice *L = &s->L;
+    /* every (direction, target node) is written by exactly one source */
+#pragma omp parallel for collapse(2) schedule(static)
     for (int z = 0; z < s->nz; z++)
         for (int y = 0; y < s->ny; y++)
             for (int x = 0; x < s->nx; x++) {
@@ -635,6 +673,7 @@ static void stream_all(orc_sim *s) {
 /* Eq. (3) with shares: F_p = -sum_n s_pn q_n, T_p = -sum_n r_pn x (s_pn q_n). */
 static void hydro_forces(orc_sim *s) {
     const int D = s->L.D;
+#pragma omp parallel for schedule(dynamic, 16)
     for (int p = 0; p < s->np; p++) {
         orc_acc F[3] = {{0, 0}, {0, 0}, {0, 0}}, T[3] = {{0, 0}, {0, 0}, {0, 0}};
         int lo[3], hi[3];
@@ -678,6 +717,7 @@ static void hydro_forces(orc_sim *s) {
 static void dem_forces_impl(int D, int np, const double *x, const double *v,
                             const double *R, const double *m, double kn, double ce,
                             const double Lbox[3], int wall_y, double *Fc) {
+#pragma omp parallel for schedule(dynamic, 16)
     for (int i = 0; i < np; i++) {
         double F[3] = {0.0, 0.0, 0.0};
         for (int j = 0; j < np; j++) {
@@ -745,6 +785,7 @@ static double wrap_pos(double x, double Lp) {
 static void integrate(orc_sim *s) {
     const int D = s->L.D;
     double Lb[3] = {(double)s->nx, (double)s->ny, (double)s->nz};
+#pragma omp parallel for schedule(static)
     for (int p = 0; p < s->np; p++) {
         if (s->fixed[p]) continue;
         for (int a = 0; a < D; a++) {
@@ -836,3 +877,17 @@ double orc_sum2(const double *p, long n) {
 }
 
 double orc_beta(double eps, double tau) { return beta_of_eps(eps, tau); }
+
+/* Number of threads the oracle's parallel loops use from now on (n >= 1;
+ * n <= 0 selects every core).  Returns the number in effect; 1 when built
+ * without OpenMP. */
+int orc_set_threads(int n) {
+#ifdef _OPENMP
+    if (n <= 0) n = omp_get_num_procs();
+    omp_set_num_threads(n);
+    return omp_get_max_threads();
+#else
+    (void)n;
+    return 1;
+#endif
+}

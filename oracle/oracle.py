@@ -55,8 +55,16 @@ def lib():
         L.orc_set_eps_mode.restype = C.c_int
         L.orc_eps_table_count.argtypes = [C.c_int, C.c_int, C.c_double, C.c_double, C.c_double, C.c_double]
         L.orc_eps_table_count.restype = C.c_int
+        L.orc_set_threads.argtypes = [C.c_int]
+        L.orc_set_threads.restype = C.c_int
         _lib = L
     return _lib
+
+
+def set_threads(n):
+    """Threads of the oracle's parallel loops from now on (n <= 0: every
+    core); returns the number in effect.  Results do not depend on it."""
+    return lib().orc_set_threads(int(n))
 
 
 def _dp(a):
