@@ -110,9 +110,11 @@ int lbm_create(const lbm_config *cfg, void *workspace, size_t ws_bytes,
 
 void lbm_destroy(lbm_ctx *ctx);
 
-/* Replaces the particle set.  pos/vel/omega [n][3], radius/rho_s [n],
+/* Replaces the particle set (n may be 0: a fluid without particles; some
+ * call of lbm_set_particles or lbm_load must precede the first lbm_step).
+ * pos/vel/omega [n][3], radius/rho_s [n],
  * fixed [n] (1: the particle never moves; its force and torque are still
- * reported).  Mass is rho_s pi R^2 (disc of unit depth) or rho_s 4/3 pi R^3,
+ * reported).  Clears the health flags a failed lbm_step left set.  Mass is rho_s pi R^2 (disc of unit depth) or rho_s 4/3 pi R^3,
  * moment of inertia m R^2 / 2 or 2 m R^2 / 5.  `fixed` may be NULL.  Host
  * pointers only for this call (ptr_kind must be LBM_HOST).  Errors:
  * LBM_E_INVALID (n > max_particles, radius <= 0 or > max_radius, a particle wider than the
@@ -134,9 +136,13 @@ int lbm_get_distributions(lbm_ctx *ctx, double *f, int ptr_kind);
  * fraction; fused pull streaming + LBGK/IMB collision (Eqs. 1-2); hydrodynamic
  * force and torque per particle (Eq. 3); DEM contacts (Eqs. 4-5); symplectic
  * Euler update of the particles.  Returns after the work is queued and the
- * health flags of the call are read back (which synchronises the stream).
- * Errors: LBM_E_SLOT_OVERFLOW, LBM_E_CELL_OVERFLOW, LBM_E_CONTACT_OVERFLOW,
- * LBM_E_HIP, LBM_E_STATE. */
+ * health flags are read back (which synchronises the stream).  The flags
+ * stay set once raised: after an error the state is not a valid step of the
+ * method, and every later lbm_step reports the same error until
+ * lbm_set_particles or lbm_load replaces the state.
+ * Errors: LBM_E_STATE (no lbm_set_particles or lbm_load yet),
+ * LBM_E_SLOT_OVERFLOW, LBM_E_CELL_OVERFLOW, LBM_E_CONTACT_OVERFLOW,
+ * LBM_E_NONFINITE, LBM_E_HIP. */
 int lbm_step(lbm_ctx *ctx, int64_t nsteps);
 
 /* Hydrodynamic force and torque on each particle from the last completed
@@ -217,10 +223,38 @@ int lbm_autotune_lattice_block(lbm_ctx *ctx, int steps, int *best_threads, int *
                                int *best_cu_groups, double *ms_out);
 
 /* Writes / reads the full state (populations in storage format, particles,
- * forces, time) to / from a file.  The file records the configuration; a
- * mismatching file gives LBM_E_INVALID. */
+ * forces, time) to / from a file.  The file records the configuration.
+ * lbm_load reads and checks the whole file before it changes anything: a
+ * file of another configuration or with particles that lbm_set_particles
+ * would reject gives LBM_E_INVALID, a short, overlong or unreadable file
+ * LBM_E_IO, and in both cases the context keeps its state.  A loaded state
+ * rebuilds the DEM cell grid from its radii and starts with clear health
+ * flags. */
 int lbm_save(lbm_ctx *ctx, const char *path);
 int lbm_load(lbm_ctx *ctx, const char *path);
+
+/* Suspension-wide sums of the current state ("Simulation results": the
+ * temporal evolution of the area-averaged inter-phase slip velocity and of the
+ * drag, Figs. 5 and 7).  Node sums run over the pre-collision populations
+ * f(x, t); eps_n is the solid fraction of the last completed step's footprint
+ * (zero everywhere before the first step).  Reductions have a fixed order,
+ * so a state gives the same bits every time.  Synchronises the stream. */
+typedef struct lbm_stats {
+    int64_t t;                      /* completed time steps */
+    int64_t np;                     /* particles */
+    int64_t nodes;                  /* lattice nodes N */
+    double mass;                    /* sum_n rho_n */
+    double fluid_momentum[3];       /* sum_n sum_i c_i f_i */
+    double solid_fraction;          /* sum_n eps_n / N */
+    double fluid_velocity[3];       /* fluid phase: sum_n (1 - eps_n) j_n / sum_n (1 - eps_n) rho_n */
+    double particle_momentum[3];    /* sum_p m_p v_p */
+    double particle_velocity[3];    /* sum_p m_p v_p / sum_p m_p */
+    double mean_particle_velocity[3]; /* (1/np) sum_p v_p */
+    double slip_velocity[3];        /* fluid_velocity - particle_velocity */
+    double mean_drag[3];            /* (1/np) sum_p F^h_p of the last step (Eq. 3) */
+} lbm_stats;
+
+int lbm_get_stats(lbm_ctx *ctx, lbm_stats *out);
 
 /* ------------------------------------------------ batched drag ensemble
  * Many small fully periodic cubic D3Q19 boxes, each with fixed equal spheres

@@ -34,6 +34,14 @@ class lbm_config(C.Structure):
                 ("max_particles", C.c_int), ("max_radius", C.c_double), ("eps_mode", C.c_int)]
 
 
+class lbm_stats(C.Structure):
+    _fields_ = [("t", C.c_int64), ("np", C.c_int64), ("nodes", C.c_int64), ("mass", C.c_double),
+                ("fluid_momentum", C.c_double * 3), ("solid_fraction", C.c_double),
+                ("fluid_velocity", C.c_double * 3), ("particle_momentum", C.c_double * 3),
+                ("particle_velocity", C.c_double * 3), ("mean_particle_velocity", C.c_double * 3),
+                ("slip_velocity", C.c_double * 3), ("mean_drag", C.c_double * 3)]
+
+
 class LbmError(RuntimeError):
     def __init__(self, code, msg=""):
         self.code = code
@@ -45,7 +53,7 @@ _SYMBOLS = ("lbm_workspace_bytes", "lbm_create", "lbm_destroy", "lbm_set_particl
             "lbm_set_distributions", "lbm_get_distributions", "lbm_step", "lbm_get_forces",
             "lbm_get_contact_forces", "lbm_get_particles", "lbm_get_macro", "lbm_get_q",
             "lbm_time", "lbm_particle_count", "lbm_set_timing", "lbm_get_timing", "lbm_save", "lbm_load",
-            "lbm_set_lattice_block", "lbm_get_lattice_block", "lbm_autotune_lattice_block",
+            "lbm_set_lattice_block", "lbm_get_lattice_block", "lbm_autotune_lattice_block", "lbm_get_stats",
             "lbm_error_string", "lbm_last_error",
             "mlp_workspace_bytes", "mlp_create", "mlp_destroy", "mlp_set_params", "mlp_get_params",
             "mlp_forward", "mlp_gradients", "mlp_train_step",
@@ -91,6 +99,7 @@ def load():
     L.lbm_set_lattice_block.argtypes = [vp, C.c_int, C.c_int, C.c_int]
     L.lbm_get_lattice_block.argtypes = [vp, ip, ip, ip]
     L.lbm_autotune_lattice_block.argtypes = [vp, C.c_int, ip, ip, ip, dp]
+    L.lbm_get_stats.argtypes = [vp, C.POINTER(lbm_stats)]
     L.lbm_save.argtypes = [vp, C.c_char_p]
     L.lbm_load.argtypes = [vp, C.c_char_p]
     L.lbm_error_string.argtypes = [C.c_int]
@@ -198,13 +207,15 @@ class Simulation:
         self.stream.synchronize()
 
     # ----------------------------------------------------------------- ABI
-    def set_particles(self, pos, vel=None, omega=None, radius=None, rho_s=None, fixed=None):
-        pos = _f64(pos, (-1, 3))
+    def set_particles(self, pos=None, vel=None, omega=None, radius=None, rho_s=None, fixed=None):
+        """Replaces the particle set; no arguments (or an empty pos) sets a
+        fluid without particles, which must still precede the first step."""
+        pos = _f64(np.zeros((0, 3)) if pos is None else pos, (-1, 3))
         n = pos.shape[0]
         vel = _f64(np.zeros((n, 3)) if vel is None else vel, (n, 3))
         omega = _f64(np.zeros((n, 3)) if omega is None else omega, (n, 3))
-        radius = _f64(radius, (n,))
-        rho_s = _f64(rho_s, (n,))
+        radius = _f64(np.zeros(n) if radius is None and n == 0 else radius, (n,))
+        rho_s = _f64(np.zeros(n) if rho_s is None and n == 0 else rho_s, (n,))
         fx = None if fixed is None else np.ascontiguousarray(np.asarray(fixed, dtype=np.uint8).reshape(n))
         self._check(load().lbm_set_particles(self._ctx, n, _ptr(pos), _ptr(vel), _ptr(omega),
                                              _ptr(radius), _ptr(rho_s), _ptr(fx), LBM_HOST))
@@ -262,6 +273,16 @@ class Simulation:
         x = np.zeros((n, 3)); v = np.zeros((n, 3)); w = np.zeros((n, 3))
         self._check(load().lbm_get_particles(self._ctx, _ptr(x), _ptr(v), _ptr(w), LBM_HOST))
         return x[: self.np_], v[: self.np_], w[: self.np_]
+
+    def stats(self):
+        """Suspension-wide sums (lbm_get_stats) as a dict of floats / 3-vectors."""
+        st = lbm_stats()
+        self._check(load().lbm_get_stats(self._ctx, C.byref(st)))
+        out = {}
+        for name, typ in lbm_stats._fields_:
+            v = getattr(st, name)
+            out[name] = np.array(list(v)) if hasattr(v, "__len__") else v
+        return out
 
     def set_timing(self, on, lattice_only=False):
         mode = 0 if not on else (2 if lattice_only else 1)

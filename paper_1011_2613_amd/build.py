@@ -16,7 +16,7 @@ ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "liblbimb.so")
 BUILD = os.path.join(HERE, "_build")
 
-SOURCES = ["lb_kernels.hip", "particle_kernels.hip", "runtime.hip", "mlp.hip", "batch.hip", "batch_host.hip"]
+SOURCES = ["lb_kernels.hip", "particle_kernels.hip", "runtime.hip", "mlp.hip", "batch.hip", "batch_host.hip", "stats.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17", "-ffp-contract=off",

@@ -159,6 +159,27 @@ struct CellArgs {
     double ap[3];
 };
 
+// Suspension-wide sums (lbm_get_stats): node pass over the lattice rows with a
+// fixed number of workgroups, one row of STATS_PK values per particle, one
+// final workgroup.  tot receives 4 + STATS_PK values: mass, j (3), then the
+// particle sums m v (3), v (3), F^h (3), eps-share of mass, of momentum (3),
+// eps (the node's solid fraction split over its owners), m.
+constexpr int STATS_NT = 256;
+constexpr int STATS_NODE_GROUPS = 1024;
+constexpr int STATS_PK = 15;
+
+struct StatsArgs {
+    const void *A;         // current state (pre-collision populations by pull)
+    Geom g;
+    Particles P;
+    const void *qr;        // exchange records of the last step (node totals)
+    int rec32;
+    int Smax;
+    double *node_part;     // [STATS_NODE_GROUPS][4]
+    double *part_rows;     // [np][STATS_PK]
+    double *tot;           // [4 + STATS_PK]
+};
+
 // One periodic cubic box of the batched ensemble (fixed spheres).
 struct BatchBox {
     int L;                 // edge
@@ -225,6 +246,9 @@ hipError_t launch_macro(int lattice, int storage, const Geom &g, const void *A, 
                         double *u, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t *p, uint32_t value, int64_t count, hipStream_t s);
 hipError_t launch_fill_u64(uint64_t *p, uint64_t value, int64_t count, hipStream_t s);
+
+// launcher (stats.hip)
+hipError_t launch_stats(int lattice, int storage, const StatsArgs &a, hipStream_t s);
 
 // launchers (particle_kernels.hip)
 hipError_t launch_foot_paint(const FootArgs &a, int D, hipStream_t s);

@@ -39,7 +39,7 @@ struct Layout {
     size_t off_list, off_list_len;
     int list_cap;
     double rmax;
-    size_t off_cc, off_cid, off_flags, off_tab, total;
+    size_t off_cc, off_cid, off_flags, off_tab, off_stats, total;
 };
 
 int validate(const lbm_config *c, std::string &msg) {
@@ -106,6 +106,8 @@ Layout make_layout(const lbm_config *c) {
     L.off_cid = take((size_t)L.cell_budget * CELL_CAP * 4);
     L.off_flags = take(64);
     L.off_tab = take((size_t)EPS_TAB_NRHO * EPS_TAB_NT * EPS_TAB_NT * 2);
+    // lbm_get_stats: node-pass partials, one row per particle, the totals
+    L.off_stats = take(((size_t)STATS_NODE_GROUPS * 4 + P * STATS_PK + 4 + STATS_PK) * 8);
     L.total = o;
     return L;
 }
@@ -195,6 +197,37 @@ Particles particles(lbm_ctx *c) {
 void *state(lbm_ctx *c, int which) { return c->ws + (which == 0 ? c->L.off_fA : c->L.off_fB); }
 
 uint32_t *flags(lbm_ctx *c) { return wsp<uint32_t>(c, c->L.off_flags); }
+
+// DEM cell grid for np particles of largest radius rmax: cell edge >= 2 rmax,
+// the count bounded by the reserved budget.
+void cell_grid(const lbm_ctx *c, int np, double rmax, int nc[3]) {
+    const double Lb[3] = {c->g.Lx, c->g.Ly, c->g.Lz};
+    nc[0] = nc[1] = nc[2] = 1;
+    if (np < 1) return;
+    for (int a = 0; a < c->L.D; a++) nc[a] = std::max(1, (int)std::floor(Lb[a] / (2.0 * rmax)));
+    while ((int64_t)nc[0] * nc[1] * nc[2] > c->L.cell_budget)
+        for (int a = 0; a < c->L.D; a++) nc[a] = std::max(1, nc[a] / 2);
+}
+
+// Checks one particle's radius and state against the context (the rules of
+// lbm_set_particles; pos, vel, omega point at its three components): true if
+// it passes, else a message in `why`.
+bool particle_ok(const lbm_ctx *c, double r, const double *pos, const double *vel,
+                 const double *omega, const char *&why) {
+    const double Lb[3] = {c->g.Lx, c->g.Ly, c->g.Lz};
+    if (!(r > 0.0) || !std::isfinite(r)) { why = "radius must be > 0"; return false; }
+    if (r > c->L.rmax) { why = "radius above max_radius"; return false; }
+    for (int a = 0; a < 3; a++)
+        if ((a < c->L.D || a == 2) && !std::isfinite(omega[a])) { why = "non-finite angular velocity"; return false; }
+    for (int a = 0; a < c->L.D; a++) {
+        if (!std::isfinite(pos[a]) || !std::isfinite(vel[a])) { why = "non-finite state"; return false; }
+        const bool periodic = !(a == 1 && c->g.wall_y);
+        if (periodic && (pos[a] < 0.0 || pos[a] >= Lb[a])) { why = "centre outside the periodic box"; return false; }
+        if (periodic && 2.0 * r + 2.0 > Lb[a]) { why = "wider than the periodic box"; return false; }
+    }
+    if (c->g.wall_y && (pos[1] < -0.5 || pos[1] > Lb[1] - 0.5)) { why = "centre beyond a wall"; return false; }
+    return true;
+}
 
 CellArgs cell_args(lbm_ctx *c) {
     CellArgs a;
@@ -606,34 +639,19 @@ int lbm_set_particles(lbm_ctx *c, int64_t n, const double *pos, const double *ve
     double rmax = 0.0;
     const int P = (int)n;
     for (int p = 0; p < P; p++) {
-        const double r = radius[p];
-        if (!(r > 0.0) || !std::isfinite(r)) return fail(c, LBM_E_INVALID, "particle %d: radius must be > 0", p);
-        if (r > c->L.rmax) return fail(c, LBM_E_INVALID, "particle %d: radius %g above max_radius %g", p, r, c->L.rmax);
-        if (!(rho_s[p] > 0.0) || !std::isfinite(rho_s[p])) return fail(c, LBM_E_INVALID, "particle %d: density must be > 0", p);
-        for (int a = 0; a < D; a++) {
-            if (!std::isfinite(pos[3 * p + a]) || !std::isfinite(vel[3 * p + a]))
-                return fail(c, LBM_E_INVALID, "particle %d: non-finite state", p);
-            const bool periodic = !(a == 1 && c->g.wall_y);
-            if (periodic && (pos[3 * p + a] < 0.0 || pos[3 * p + a] >= Lb[a]))
-                return fail(c, LBM_E_INVALID, "particle %d: centre outside the periodic box", p);
-            if (periodic && 2.0 * r + 2.0 > Lb[a])
-                return fail(c, LBM_E_INVALID, "particle %d: wider than the periodic box", p);
-        }
-        if (c->g.wall_y && (pos[3 * p + 1] < -0.5 || pos[3 * p + 1] > Lb[1] - 0.5))
-            return fail(c, LBM_E_INVALID, "particle %d: centre beyond a wall", p);
-        rmax = std::max(rmax, r);
+        const char *why = "";
+        if (!particle_ok(c, radius[p], pos + 3 * p, vel + 3 * p, omega + 3 * p, why))
+            return fail(c, LBM_E_INVALID, "particle %d: %s", p, why);
+        if (!(rho_s[p] > 0.0) || !std::isfinite(rho_s[p]))
+            return fail(c, LBM_E_INVALID, "particle %d: density must be > 0", p);
+        rmax = std::max(rmax, radius[p]);
     }
     if (c->cfg.eps_mode == LBM_EPS_TABLE) {
         const int r = upload_eps_table(c, radius, P);
         if (r != LBM_OK) return r;
     }
-    // DEM cells: edge >= 2 R_max, count bounded by the reserved budget
-    int nc[3] = {1, 1, 1};
-    if (P > 0) {
-        for (int a = 0; a < D; a++) nc[a] = std::max(1, (int)std::floor(Lb[a] / (2.0 * rmax)));
-        while ((int64_t)nc[0] * nc[1] * nc[2] > c->L.cell_budget)
-            for (int a = 0; a < D; a++) nc[a] = std::max(1, nc[a] / 2);
-    }
+    int nc[3];
+    cell_grid(c, P, rmax, nc);
     // overlap check on the host with the same cell grid
     if (P > 1) {
         const int ncell = nc[0] * nc[1] * nc[2];
@@ -727,6 +745,8 @@ int lbm_set_particles(lbm_ctx *c, int64_t n, const double *pos, const double *ve
     HIPCHK(c, launch_fill_u32(wsp<uint32_t>(c, c->L.off_Th), 0u, (int64_t)(3 * np * 2), c->stream));
     HIPCHK(c, launch_fill_u32(wsp<uint32_t>(c, c->L.off_Fc), 0u, (int64_t)(3 * np * 2), c->stream));
     HIPCHK(c, launch_fill_u32(wsp<uint32_t>(c, c->L.off_list_len), 0u, (int64_t)np, c->stream));
+    // a new particle set starts with clear health flags
+    HIPCHK(c, launch_fill_u32(flags(c), 0u, 16, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     c->particles_set = true;
     return LBM_OK;
@@ -843,6 +863,8 @@ int64_t lbm_particle_count(const lbm_ctx *c) { return c ? c->np : -1; }
 
 int lbm_step(lbm_ctx *c, int64_t nsteps) {
     if (!c || nsteps < 0) return LBM_E_INVALID;
+    if (!c->particles_set)
+        return fail(c, LBM_E_STATE, "lbm_step before lbm_set_particles (n may be 0) or lbm_load");
     if (nsteps == 0) return LBM_OK;
     hipError_t e;
     if (c->timing) {
@@ -1015,6 +1037,9 @@ int lbm_save(lbm_ctx *c, const char *path) {
     return ok ? LBM_OK : fail(c, LBM_E_IO, "write failed: %s", path);
 }
 
+// Reads the whole file and checks it before anything in the context
+// changes: a truncated, foreign or inconsistent file leaves the context as it
+// was.  The DEM cell grid is rebuilt from the loaded radii.
 int lbm_load(lbm_ctx *c, const char *path) {
     if (!c || !path) return LBM_E_INVALID;
     FILE *fp = fopen(path, "rb");
@@ -1032,41 +1057,107 @@ int lbm_load(lbm_ctx *c, const char *path) {
     if (!ok || magic != SAVE_MAGIC) { fclose(fp); return fail(c, LBM_E_IO, "not a state file: %s", path); }
     if (memcmp(&cfg, &c->cfg, sizeof(cfg)) != 0) { fclose(fp); return fail(c, LBM_E_INVALID, "state file has another configuration"); }
     if (np < 0 || np > c->cfg.max_particles) { fclose(fp); return fail(c, LBM_E_INVALID, "bad particle count in file"); }
-    HIPCHK(c, hipStreamSynchronize(c->stream));
-    drop_graphs(c);
-    c->np = np;
+    if (t < 0) { fclose(fp); return fail(c, LBM_E_INVALID, "bad time in file"); }
     const size_t fbytes = (size_t)c->L.Q * c->L.N * store_bytes(c->cfg.storage);
     const size_t P = (size_t)std::max(np, 1);
-    std::vector<char> buf(std::max(fbytes, 16 * P * 8));
-    get(buf.data(), fbytes);
-    if (ok && hipMemcpy(state(c, 0), buf.data(), fbytes, hipMemcpyHostToDevice) != hipSuccess) ok = false;
-    const size_t offs[] = {c->L.off_x, c->L.off_v, c->L.off_w, c->L.off_Fh, c->L.off_Th, c->L.off_Fc};
-    for (size_t o : offs) {
-        get(buf.data(), 3 * P * 8);
-        if (ok && hipMemcpy(c->ws + o, buf.data(), 3 * P * 8, hipMemcpyHostToDevice) != hipSuccess) ok = false;
+    std::vector<char> fbuf(fbytes);
+    get(fbuf.data(), fbytes);
+    std::vector<double> vec[6];  // x, v, omega, F^h, T^h, F^c as [3][np]
+    for (auto &v : vec) {
+        v.resize(3 * P);
+        get(v.data(), 3 * P * 8);
     }
-    const size_t offs1[] = {c->L.off_R, c->L.off_m, c->L.off_I};
-    std::vector<double> radii(P);
-    for (size_t o : offs1) {
-        get(buf.data(), P * 8);
-        if (o == c->L.off_R) memcpy(radii.data(), buf.data(), P * 8);
-        if (ok && hipMemcpy(c->ws + o, buf.data(), P * 8, hipMemcpyHostToDevice) != hipSuccess) ok = false;
-    }
-    get(buf.data(), P);
-    if (ok && hipMemcpy(c->ws + c->L.off_fixed, buf.data(), P, hipMemcpyHostToDevice) != hipSuccess) ok = false;
-    get(&c->ncx, 4); get(&c->ncy, 4); get(&c->ncz, 4);
+    std::vector<double> R(P), M(P), I(P);
+    get(R.data(), P * 8);
+    get(M.data(), P * 8);
+    get(I.data(), P * 8);
+    std::vector<uint8_t> fixed(P);
+    get(fixed.data(), P);
+    int ncf[3];
+    get(ncf, sizeof(ncf));  // recorded for reference; the grid is rebuilt below
+    const bool at_end = ok && fgetc(fp) == EOF;
     fclose(fp);
-    if (!ok) return fail(c, LBM_E_IO, "read failed: %s", path);
+    if (!ok) return fail(c, LBM_E_IO, "truncated state file: %s", path);
+    if (!at_end) return fail(c, LBM_E_IO, "state file longer than its contents: %s", path);
+    double rmax = 0.0;
+    for (int p = 0; p < np; p++) {
+        double pos[3], vel[3], om[3];
+        for (int a = 0; a < 3; a++) {
+            pos[a] = vec[0][(size_t)a * np + p];
+            vel[a] = vec[1][(size_t)a * np + p];
+            om[a] = vec[2][(size_t)a * np + p];
+        }
+        const char *why = "";
+        if (!particle_ok(c, R[p], pos, vel, om, why))
+            return fail(c, LBM_E_INVALID, "state file, particle %d: %s", p, why);
+        if (!(M[p] > 0.0) || !std::isfinite(M[p]) || !(I[p] > 0.0) || !std::isfinite(I[p]))
+            return fail(c, LBM_E_INVALID, "state file, particle %d: mass and inertia must be > 0", p);
+        rmax = std::max(rmax, R[p]);
+    }
     if (c->cfg.eps_mode == LBM_EPS_TABLE) {
-        const int r = upload_eps_table(c, radii.data(), np);
+        const int r = upload_eps_table(c, R.data(), np);
         if (r != LBM_OK) return r;
     }
+    int nc[3];
+    cell_grid(c, np, rmax, nc);
+    // the file is sound: replace the state
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    drop_graphs(c);
+    HIPCHK(c, hipMemcpy(state(c, 0), fbuf.data(), fbytes, hipMemcpyHostToDevice));
+    const size_t offs[6] = {c->L.off_x, c->L.off_v, c->L.off_w, c->L.off_Fh, c->L.off_Th, c->L.off_Fc};
+    for (int k = 0; k < 6; k++) HIPCHK(c, hipMemcpy(c->ws + offs[k], vec[k].data(), 3 * P * 8, hipMemcpyHostToDevice));
+    HIPCHK(c, hipMemcpy(c->ws + c->L.off_R, R.data(), P * 8, hipMemcpyHostToDevice));
+    HIPCHK(c, hipMemcpy(c->ws + c->L.off_m, M.data(), P * 8, hipMemcpyHostToDevice));
+    HIPCHK(c, hipMemcpy(c->ws + c->L.off_I, I.data(), P * 8, hipMemcpyHostToDevice));
+    HIPCHK(c, hipMemcpy(c->ws + c->L.off_fixed, fixed.data(), P, hipMemcpyHostToDevice));
+    c->np = np;
+    c->ncx = nc[0]; c->ncy = nc[1]; c->ncz = nc[2];
     c->cur = 0;
     c->t = t;
     c->particles_set = true;
     HIPCHK(c, launch_fill_u32(wsp<uint32_t>(c, c->L.off_nown), 0u, (int64_t)((c->L.N + 7) / 8 * 2), c->stream));
-    HIPCHK(c, launch_fill_u32(wsp<uint32_t>(c, c->L.off_list_len), 0u, (int64_t)std::max(np, 1), c->stream));
+    HIPCHK(c, launch_fill_u32(wsp<uint32_t>(c, c->L.off_list_len), 0u, (int64_t)P, c->stream));
+    HIPCHK(c, launch_fill_u32(flags(c), 0u, 16, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
+    return LBM_OK;
+}
+
+// Suspension-wide sums, reduced in a fixed order on the context's stream.
+int lbm_get_stats(lbm_ctx *c, lbm_stats *out) {
+    if (!c || !out) return LBM_E_INVALID;
+    StatsArgs a;
+    a.A = state(c, c->cur);
+    a.g = c->g;
+    a.P = particles(c);
+    a.qr = wsp<char>(c, c->L.off_qr);
+    a.rec32 = c->cfg.storage != LBM_FP64;
+    a.Smax = c->L.Smax;
+    double *base = wsp<double>(c, c->L.off_stats);
+    a.node_part = base;
+    a.part_rows = base + (size_t)STATS_NODE_GROUPS * 4;
+    a.tot = a.part_rows + (size_t)c->L.P * STATS_PK;
+    HIPCHK(c, launch_stats(c->cfg.lattice, c->cfg.storage, a, c->stream));
+    double s[4 + STATS_PK];
+    HIPCHK(c, hipMemcpyAsync(s, a.tot, sizeof(s), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    const int np = c->np;
+    out->t = c->t;
+    out->np = np;
+    out->nodes = c->L.N;
+    out->mass = s[0];
+    const double *mv = s + 4, *vs = s + 7, *Fs = s + 10;
+    const double wrho = s[13], *wj = s + 14, weps = s[17], msum = s[18];
+    out->solid_fraction = weps / (double)c->L.N;
+    const double fluid_mass = s[0] - wrho;
+    for (int d = 0; d < 3; d++) {
+        out->fluid_momentum[d] = s[1 + d];
+        out->fluid_velocity[d] = (s[1 + d] - wj[d]) / fluid_mass;
+        out->particle_momentum[d] = mv[d];
+        out->particle_velocity[d] = np > 0 ? mv[d] / msum : 0.0;
+        out->mean_particle_velocity[d] = np > 0 ? vs[d] / (double)np : 0.0;
+        out->slip_velocity[d] = out->fluid_velocity[d] - out->particle_velocity[d];
+        out->mean_drag[d] = np > 0 ? Fs[d] / (double)np : 0.0;
+    }
     return LBM_OK;
 }
 

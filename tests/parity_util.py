@@ -30,6 +30,8 @@ def make_pair(binding, dim, shape, tau, wall_y=False, fluid_force=(0, 0, 0),
     if particles is not None and n > 0:
         orc.set_particles(*particles)
         gpu.set_particles(*particles)
+    else:
+        gpu.set_particles()
     if f0 is not None:
         orc.set_f(f0)
         gpu.set_f(f0)

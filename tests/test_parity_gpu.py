@@ -276,8 +276,7 @@ def test_lattice_block_widths_bitwise(gpu_lib, storage):
         for width, order, cap in shapes:
             s = gpu_lib.Simulation(dim, shape, 0.62, **kw)
             s.set_f(f0)
-            if parts is not None:
-                s.set_particles(*parts)
+            s.set_particles(*(parts if parts is not None else ()))
             s.set_lattice_block(width, order, cap)
             assert s.lattice_block == (width or (192 if box[0] == 150 else 256), order, cap)
             s.step(23)
