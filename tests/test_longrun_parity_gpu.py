@@ -57,6 +57,9 @@ def _disp_err(x, xref, x0, w):
 ])
 def test_longrun_fp64_parity(gpu_lib, name, steps, shape):
     path = os.path.join(HERE, "golden", "longrun_%s_%d.npz" % (name, steps))
+    if not os.path.exists(path):
+        pytest.skip("reference data not written yet: python tests/golden/make_longrun.py %s %d"
+                    % (name, steps))
     d = np.load(path, allow_pickle=False)
     w = I.workload(name)
     assert int(d["steps"]) == steps and int(d["particles"]) == w.count
