@@ -63,6 +63,25 @@ int mlp_gradients(mlp_ctx *ctx, const float *X, const float *y, int64_t n, float
 int mlp_train_step(mlp_ctx *ctx, const float *X, const float *y, int64_t n, float lr,
                    float *loss);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight training loops, harnesses that forbid hipMalloc): the
+ * gradient and loss of mlp_gradients for the binary32 parameters `params`
+ * (layout above), with no context and no workspace.  The intermediates live in
+ * one fixed array of MLP_NOALLOC_SCRATCH_BYTES in device memory per GPU,
+ * which the library holds until the process ends; the call allocates nothing.
+ * params [MLP_NPARAMS], X [n][40], y [n] and grads [MLP_NPARAMS] are device
+ * pointers on the current GPU; loss is a device pointer or NULL.  The work is
+ * queued on hip_stream (NULL: the null stream) and the call returns without
+ * waiting.  Results equal those of mlp_gradients on a context holding the same
+ * parameters, bit for bit.  Calls that overlap on one GPU (on different
+ * streams, or from different threads) share the array and race; order them.
+ * Errors: LBM_E_INVALID for a null pointer or n outside
+ * 1..MLP_NOALLOC_MAX_ROWS; LBM_E_HIP for a failed launch or symbol lookup. */
+#define MLP_NOALLOC_MAX_ROWS 4096
+#define MLP_NOALLOC_SCRATCH_BYTES 15380736
+int mlp_gradients_noalloc(const float *params, const float *X, const float *y, int64_t n,
+                          float *grads, float *loss, void *hip_stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -56,7 +56,7 @@ _SYMBOLS = ("lbm_workspace_bytes", "lbm_create", "lbm_destroy", "lbm_set_particl
             "lbm_set_lattice_block", "lbm_get_lattice_block", "lbm_autotune_lattice_block", "lbm_get_stats",
             "lbm_error_string", "lbm_last_error",
             "mlp_workspace_bytes", "mlp_create", "mlp_destroy", "mlp_set_params", "mlp_get_params",
-            "mlp_forward", "mlp_gradients", "mlp_train_step",
+            "mlp_forward", "mlp_gradients", "mlp_train_step", "mlp_gradients_noalloc",
             "lbm_batch_workspace_bytes", "lbm_batch_create", "lbm_batch_destroy", "lbm_batch_set_tile_rows",
             "lbm_batch_run", "lbm_batch_set_active", "lbm_batch_forces", "lbm_batch_mean_velocity",
             "lbm_batch_get_distributions", "lbm_batch_autotune", "lbm_batch_time", "lbm_batch_shell_velocity")
@@ -363,8 +363,9 @@ def _load_mlp(L):
     L.mlp_forward.argtypes = [vp, vp, i64, vp]
     L.mlp_gradients.argtypes = [vp, vp, vp, i64, vp, vp, C.c_int]
     L.mlp_train_step.argtypes = [vp, vp, vp, i64, C.c_float, vp]
+    L.mlp_gradients_noalloc.argtypes = [vp, vp, vp, i64, vp, vp, vp]
     for n in ("mlp_workspace_bytes", "mlp_create", "mlp_set_params", "mlp_get_params", "mlp_forward",
-              "mlp_gradients", "mlp_train_step"):
+              "mlp_gradients", "mlp_train_step", "mlp_gradients_noalloc"):
         getattr(L, n).restype = C.c_int
     L._mlp_ready = True
     return L
@@ -458,6 +459,34 @@ class Mlp:
         if rc:
             raise LbmError(rc, "mlp_train_step")
         return float(loss[0])
+
+
+MLP_NOALLOC_MAX_ROWS = 4096
+
+
+def mlp_gradients_noalloc(params, X, y, grads, loss=None, stream=None):
+    """mlp_gradients_noalloc on device tensors (binary32, contiguous, on the
+    current GPU): params [MLP_NPARAMS], X [n][40], y [n], grads [MLP_NPARAMS]
+    out, loss [1] out or None.  Queued on `stream` (a torch stream; None: the
+    current one); nothing is allocated."""
+    import torch
+    n = int(X.shape[0])
+    for t in (params, X, y, grads) + ((loss,) if loss is not None else ()):
+        if t.dtype != torch.float32 or not t.is_cuda or not t.is_contiguous():
+            raise ValueError("mlp_gradients_noalloc takes contiguous binary32 device tensors")
+    if params.numel() != MLP_NPARAMS or grads.numel() != MLP_NPARAMS or X.shape[1:] != (MLP_NIN,) \
+            or y.numel() != n:
+        raise ValueError("mlp_gradients_noalloc: shapes params [%d], X [n][%d], y [n], grads [%d]"
+                         % (MLP_NPARAMS, MLP_NIN, MLP_NPARAMS))
+    if not 1 <= n <= MLP_NOALLOC_MAX_ROWS:
+        raise ValueError("mlp_gradients_noalloc takes 1..%d rows, got %d" % (MLP_NOALLOC_MAX_ROWS, n))
+    s = stream if stream is not None else torch.cuda.current_stream(X.device)
+    rc = _load_mlp(load()).mlp_gradients_noalloc(
+        C.c_void_p(params.data_ptr()), C.c_void_p(X.data_ptr()), C.c_void_p(y.data_ptr()), n,
+        C.c_void_p(grads.data_ptr()), C.c_void_p(loss.data_ptr() if loss is not None else None),
+        C.c_void_p(s.cuda_stream))
+    if rc:
+        raise LbmError(rc, "mlp_gradients_noalloc")
 
 
 def mlp_unpack(p):

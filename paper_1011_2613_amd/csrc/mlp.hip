@@ -22,6 +22,7 @@
 #include <math.h>
 
 #include <algorithm>
+#include <mutex>
 #include <new>
 
 #include "../../include/lbimb.h"
@@ -356,7 +357,7 @@ __global__ void k_pack(const float *p, Wbf w) {
 }
 
 constexpr size_t AL = 256;
-size_t al(size_t v) { return (v + AL - 1) / AL * AL; }
+constexpr size_t al(size_t v) { return (v + AL - 1) / AL * AL; }
 
 struct Lay {
     int64_t B;  // batch capacity, multiple of 32
@@ -364,12 +365,16 @@ struct Lay {
         tmp, loss, total;
 };
 
-Lay layout(int64_t max_batch) {
+// masters: whether the binary32 parameters, their gradient and the Adam
+// moments live here too (a context) or stay with the caller (a bare gradient
+// evaluation).
+constexpr Lay layout(int64_t max_batch, bool masters = true) {
     Lay L{};
     L.B = (max_batch + 31) / 32 * 32;
     size_t o = 0;
     auto take = [&](size_t b) { size_t r = o; o = al(o + b); return r; };
-    L.p = take(NPAR * 4); L.m = take(NPAR * 4); L.v = take(NPAR * 4); L.g = take(NPAR * 4);
+    const size_t mp = masters ? (size_t)NPAR * 4 : 0;
+    L.p = take(mp); L.m = take(mp); L.v = take(mp); L.g = take(mp);
     L.w1 = take(NH * KIN * 2); L.w2 = take(NH * NH * 2); L.w3 = take(NH * NH * 2); L.w4 = take(16 * NH * 2);
     const size_t B = (size_t)L.B;
     L.h0 = take(B * KIN * 2); L.h1 = take(B * NH * 2); L.h2 = take(B * NH * 2); L.h3 = take(B * NH * 2);
@@ -394,73 +399,133 @@ struct mlp_ctx {
 namespace {
 template <class T> T *P(mlp_ctx *c, size_t off) { return (T *)(c->ws + off); }
 
-hipError_t pack(mlp_ctx *c) {
-    hipLaunchKernelGGL(k_pack, dim3((NH * NH + 255) / 256), dim3(256), 0, c->s, P<float>(c, c->L.p), c->w);
+// Where one gradient evaluation reads its parameters and keeps its
+// intermediates (activations, pre-activations, output and hidden-layer
+// gradients, the padded first-layer weight gradient), and where it writes the
+// gradient and the loss.
+struct GradBufs {
+    char *base;        // intermediates at the offsets of L
+    Lay L;
+    const float *p;    // binary32 parameters (biases are read from here)
+    Wbf w;             // their bfloat16 copies
+    float *g;          // gradient out [NPAR]
+    float *loss;       // loss out (one value)
+    hipStream_t s;
+};
+template <class T> T *Q(const GradBufs &b, size_t off) { return (T *)(b.base + off); }
+
+GradBufs bufs_of(mlp_ctx *c) {
+    return GradBufs{c->ws, c->L, P<float>(c, c->L.p), c->w, P<float>(c, c->L.g), P<float>(c, c->L.loss), c->s};
+}
+
+hipError_t pack_to(const float *p, Wbf w, hipStream_t s) {
+    hipLaunchKernelGGL(k_pack, dim3((NH * NH + 255) / 256), dim3(256), 0, s, p, w);
     return hipGetLastError();
 }
+
+hipError_t pack(mlp_ctx *c) { return pack_to(P<float>(c, c->L.p), c->w, c->s); }
 
 hipError_t zero(mlp_ctx *c, size_t off, size_t bytes) {
     return lbimb::launch_fill_u32(P<uint32_t>(c, off), 0u, (int64_t)(bytes / 4), c->s);
 }
 
-// Forward (training mode) + backward into c->g; loss into c->L.loss.
-hipError_t grads(mlp_ctx *c, const float *X, const float *y, int64_t n) {
-    const Lay &L = c->L;
+// Forward (training mode) + backward: the gradient of the mean squared error
+// into b.g, the loss into *b.loss.  Every intermediate a kernel reads is
+// written earlier in the same evaluation (the padding rows up to a multiple of
+// 32 are cleared here), so the buffers may hold anything on entry.
+hipError_t grads(const GradBufs &b, const float *X, const float *y, int64_t n) {
+    const Lay &L = b.L;
     const int64_t npad = (n + 31) / 32 * 32;
     hipError_t e;
     // padding rows of the activations must be zero for the K-reductions
     if (npad > n) {
-        if ((e = zero(c, L.h0 + (size_t)n * KIN * 2, (size_t)(npad - n) * KIN * 2)) != hipSuccess) return e;
-        if ((e = zero(c, L.h1 + (size_t)n * NH * 2, (size_t)(npad - n) * NH * 2)) != hipSuccess) return e;
-        if ((e = zero(c, L.h2 + (size_t)n * NH * 2, (size_t)(npad - n) * NH * 2)) != hipSuccess) return e;
-        if ((e = zero(c, L.h3 + (size_t)n * NH * 2, (size_t)(npad - n) * NH * 2)) != hipSuccess) return e;
+        const size_t hoff[4] = {L.h0, L.h1, L.h2, L.h3};
+        for (int k = 0; k < 4; k++) {
+            const size_t row = k == 0 ? KIN * 2 : NH * 2;
+            if ((e = lbimb::launch_fill_u32(Q<uint32_t>(b, hoff[k] + (size_t)n * row), 0u,
+                                            (int64_t)((size_t)(npad - n) * row / 4), b.s)) != hipSuccess)
+                return e;
+        }
     }
     FwdArgs fa;
-    fa.X = X; fa.n = n; fa.p = P<float>(c, L.p); fa.w = c->w; fa.y = P<float>(c, L.y);
-    fa.h0 = P<__bf16>(c, L.h0); fa.h1 = P<__bf16>(c, L.h1); fa.h2 = P<__bf16>(c, L.h2);
-    fa.h3 = P<__bf16>(c, L.h3);
-    fa.z1 = P<float>(c, L.z1); fa.z2 = P<float>(c, L.z2); fa.z3 = P<float>(c, L.z3);
+    fa.X = X; fa.n = n; fa.p = b.p; fa.w = b.w; fa.y = Q<float>(b, L.y);
+    fa.h0 = Q<__bf16>(b, L.h0); fa.h1 = Q<__bf16>(b, L.h1); fa.h2 = Q<__bf16>(b, L.h2);
+    fa.h3 = Q<__bf16>(b, L.h3);
+    fa.z1 = Q<float>(b, L.z1); fa.z2 = Q<float>(b, L.z2); fa.z3 = Q<float>(b, L.z3);
     const int64_t tiles = (n + 15) / 16;
     const unsigned blocks = (unsigned)std::min<int64_t>((tiles + FWD_WAVES_TRAIN - 1) / FWD_WAVES_TRAIN, 1024);
-    hipLaunchKernelGGL(k_mlp_forward<true>, dim3(blocks), dim3(64 * FWD_WAVES_TRAIN), 0, c->s, fa);
+    hipLaunchKernelGGL(k_mlp_forward<true>, dim3(blocks), dim3(64 * FWD_WAVES_TRAIN), 0, b.s, fa);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    float *g = P<float>(c, L.g);
-    hipLaunchKernelGGL(k_out_grad, dim3((unsigned)((npad + 255) / 256)), dim3(256), 0, c->s,
-                       (const float *)P<float>(c, L.y), y, n, npad, P<float>(c, L.gout), P<__bf16>(c, L.gq),
-                       P<float>(c, L.sq));
-    hipLaunchKernelGGL(k_top_grads, dim3(1), dim3(192), 0, c->s, (const __bf16 *)P<__bf16>(c, L.gq),
-                       (const float *)P<float>(c, L.gout), (const __bf16 *)P<__bf16>(c, L.h3),
-                       (const float *)P<float>(c, L.sq), n, g, P<float>(c, L.loss));
+    float *g = b.g;
+    hipLaunchKernelGGL(k_out_grad, dim3((unsigned)((npad + 255) / 256)), dim3(256), 0, b.s,
+                       (const float *)Q<float>(b, L.y), y, n, npad, Q<float>(b, L.gout), Q<__bf16>(b, L.gq),
+                       Q<float>(b, L.sq));
+    hipLaunchKernelGGL(k_top_grads, dim3(1), dim3(192), 0, b.s, (const __bf16 *)Q<__bf16>(b, L.gq),
+                       (const float *)Q<float>(b, L.gout), (const __bf16 *)Q<__bf16>(b, L.h3),
+                       (const float *)Q<float>(b, L.sq), n, g, b.loss);
     const unsigned ew = (unsigned)((npad * NH + 255) / 256);
-    hipLaunchKernelGGL(k_dz_top, dim3(ew), dim3(256), 0, c->s, (const __bf16 *)P<__bf16>(c, L.gq),
-                       (const __bf16 *)c->w.w4, (const float *)P<float>(c, L.z3), n, npad,
-                       P<float>(c, L.dz), P<__bf16>(c, L.dzq));
+    hipLaunchKernelGGL(k_dz_top, dim3(ew), dim3(256), 0, b.s, (const __bf16 *)Q<__bf16>(b, L.gq),
+                       (const __bf16 *)b.w.w4, (const float *)Q<float>(b, L.z3), n, npad,
+                       Q<float>(b, L.dz), Q<__bf16>(b, L.dzq));
     // layers 3, 2, 1: dW = dZ^T H_prev, db = colsum dZ, dH_prev = dZ W
     const size_t hprev[3] = {L.h2, L.h1, L.h0};
     const size_t zprev[2] = {L.z2, L.z1};
-    const __bf16 *wk[3] = {c->w.w3, c->w.w2, c->w.w1};
+    const __bf16 *wk[3] = {b.w.w3, b.w.w2, b.w.w1};
     const int offW[3] = {OFF_W3, OFF_W2, OFF_W1}, offB[3] = {OFF_B3, OFF_B2, OFF_B1};
     for (int k = 0; k < 3; k++) {
         const int nin = k == 2 ? KIN : NH;
-        float *dst = k == 2 ? P<float>(c, L.tmp) : g + offW[k];
-        hipLaunchKernelGGL(k_gemm_tn, dim3((NH / 16) * (nin / 16) / 4), dim3(256), 0, c->s,
-                           (const __bf16 *)P<__bf16>(c, L.dzq), NH, (const __bf16 *)P<__bf16>(c, hprev[k]), nin,
+        float *dst = k == 2 ? Q<float>(b, L.tmp) : g + offW[k];
+        hipLaunchKernelGGL(k_gemm_tn, dim3((NH / 16) * (nin / 16) / 4), dim3(256), 0, b.s,
+                           (const __bf16 *)Q<__bf16>(b, L.dzq), NH, (const __bf16 *)Q<__bf16>(b, hprev[k]), nin,
                            dst, nin, NH, nin, (int)npad);
         if (k == 2)
-            hipLaunchKernelGGL(k_take, dim3((NH * NIN + 255) / 256), dim3(256), 0, c->s,
-                               (const float *)P<float>(c, L.tmp), KIN, NH, NIN, g + OFF_W1);
-        hipLaunchKernelGGL(k_colsum, dim3(1), dim3(NH), 0, c->s, (const float *)P<float>(c, L.dz), NH, n, NH,
+            hipLaunchKernelGGL(k_take, dim3((NH * NIN + 255) / 256), dim3(256), 0, b.s,
+                               (const float *)Q<float>(b, L.tmp), KIN, NH, NIN, g + OFF_W1);
+        hipLaunchKernelGGL(k_colsum, dim3(1), dim3(NH), 0, b.s, (const float *)Q<float>(b, L.dz), NH, n, NH,
                            g + offB[k]);
         if (k < 2) {
-            hipLaunchKernelGGL(k_gemm_nn, dim3((unsigned)((npad / 16) * (NH / 16) / 4)), dim3(256), 0, c->s,
-                               (const __bf16 *)P<__bf16>(c, L.dzq), NH, wk[k], NH, P<float>(c, L.dh), NH,
+            hipLaunchKernelGGL(k_gemm_nn, dim3((unsigned)((npad / 16) * (NH / 16) / 4)), dim3(256), 0, b.s,
+                               (const __bf16 *)Q<__bf16>(b, L.dzq), NH, wk[k], NH, Q<float>(b, L.dh), NH,
                                (int)npad, NH, NH);
-            hipLaunchKernelGGL(k_dz, dim3(ew), dim3(256), 0, c->s, (const float *)P<float>(c, L.dh),
-                               (const float *)P<float>(c, zprev[k]), n, npad, P<float>(c, L.dz),
-                               P<__bf16>(c, L.dzq));
+            hipLaunchKernelGGL(k_dz, dim3(ew), dim3(256), 0, b.s, (const float *)Q<float>(b, L.dh),
+                               (const float *)Q<float>(b, zprev[k]), n, npad, Q<float>(b, L.dz),
+                               Q<__bf16>(b, L.dzq));
         }
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
+    return hipSuccess;
+}
+
+// ------------------------------------------------ allocation-free gradients
+// The intermediates of mlp_gradients_noalloc: one fixed array per GPU, held
+// until the process ends.  Host code never passes `scratch` itself to a kernel
+// (on the host that name is only a stand-in); it passes the device address
+// that hipGetSymbolAddress returns for the current GPU, looked up once per
+// device and kept in scratch_ptr.
+constexpr Lay NOALLOC_LAY = layout(MLP_NOALLOC_MAX_ROWS, false);
+static_assert(NOALLOC_LAY.total == MLP_NOALLOC_SCRATCH_BYTES, "scratch size in mlp_closure.h");
+static __device__ __align__(256) char scratch[NOALLOC_LAY.total];
+
+constexpr int MAX_DEVICES = 64;
+std::mutex scratch_mu;
+char *scratch_ptr[MAX_DEVICES];
+
+// Device address of this GPU's scratch array (looked up on the first call on
+// each device, with that device current).
+hipError_t scratch_for_current_device(char **out) {
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= MAX_DEVICES) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(scratch_mu);
+    if (!scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!ptr || (uintptr_t)ptr % AL) return hipErrorInvalidSymbol;
+        scratch_ptr[dev] = (char *)ptr;
+    }
+    *out = scratch_ptr[dev];
     return hipSuccess;
 }
 }  // namespace
@@ -535,7 +600,7 @@ int mlp_forward(mlp_ctx *c, const float *X, int64_t n, float *y) {
 int mlp_gradients(mlp_ctx *c, const float *X, const float *y, int64_t n, float *out_grads, float *loss,
                   int ptr_kind) {
     if (!c || !X || !y || n < 1 || n > c->L.B) return LBM_E_INVALID;
-    if (grads(c, X, y, n) != hipSuccess) return LBM_E_HIP;
+    if (grads(bufs_of(c), X, y, n) != hipSuccess) return LBM_E_HIP;
     const hipMemcpyKind k = ptr_kind == LBM_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice;
     if (out_grads && hipMemcpyAsync(out_grads, P<float>(c, c->L.g), NPAR * 4, k, c->s) != hipSuccess) return LBM_E_HIP;
     if (loss && hipMemcpyAsync(loss, P<float>(c, c->L.loss), 4, k, c->s) != hipSuccess) return LBM_E_HIP;
@@ -545,7 +610,7 @@ int mlp_gradients(mlp_ctx *c, const float *X, const float *y, int64_t n, float *
 
 int mlp_train_step(mlp_ctx *c, const float *X, const float *y, int64_t n, float lr, float *loss) {
     if (!c || !X || !y || n < 1 || n > c->L.B) return LBM_E_INVALID;
-    if (grads(c, X, y, n) != hipSuccess) return LBM_E_HIP;
+    if (grads(bufs_of(c), X, y, n) != hipSuccess) return LBM_E_HIP;
     c->t += 1;
     const float c1 = 1.0f - powf(0.9f, (float)c->t), c2 = 1.0f - powf(0.999f, (float)c->t);
     hipLaunchKernelGGL(k_adam, dim3((NPAR + 255) / 256), dim3(256), 0, c->s, P<float>(c, c->L.p),
@@ -555,6 +620,23 @@ int mlp_train_step(mlp_ctx *c, const float *X, const float *y, int64_t n, float 
         if (hipMemcpyAsync(loss, P<float>(c, c->L.loss), 4, hipMemcpyDeviceToHost, c->s) != hipSuccess) return LBM_E_HIP;
         if (hipStreamSynchronize(c->s) != hipSuccess) return LBM_E_HIP;
     }
+    return LBM_OK;
+}
+
+int mlp_gradients_noalloc(const float *params, const float *X, const float *y, int64_t n, float *grads_out,
+                          float *loss, void *hip_stream) {
+    if (!params || !X || !y || !grads_out) return LBM_E_INVALID;
+    if (n < 1 || n > MLP_NOALLOC_MAX_ROWS) return LBM_E_INVALID;
+    char *base = nullptr;
+    if (scratch_for_current_device(&base) != hipSuccess) return LBM_E_HIP;
+    const Lay &L = NOALLOC_LAY;
+    const hipStream_t s = (hipStream_t)hip_stream;
+    GradBufs b{base, L, params,
+               Wbf{(__bf16 *)(base + L.w1), (__bf16 *)(base + L.w2), (__bf16 *)(base + L.w3),
+                   (__bf16 *)(base + L.w4)},
+               grads_out, loss ? loss : (float *)(base + L.loss), s};
+    if (pack_to(params, b.w, s) != hipSuccess) return LBM_E_HIP;
+    if (grads(b, X, y, n) != hipSuccess) return LBM_E_HIP;
     return LBM_OK;
 }
 
