@@ -298,6 +298,48 @@ int lbm_batch_set_tile_rows(lbm_batch *b, int edge, int rows);
  * (a persistent wait hit its bound). */
 int lbm_batch_run(lbm_batch *b, int64_t nsteps, int mode);
 
+/* Advances the active boxes until each one's drag is steady, at most
+ * max_steps steps.  Every check_every steps (the last chunk may be shorter)
+ * the device computes the hydrodynamic forces (Eq. 3) and, for each active box
+ * with spheres, retires it when max over its spheres and components of
+ * |F - F_prev| < tol * (mean over its spheres of |F|), F_prev being the force
+ * at the previous check of this call (the first check only records it).
+ * Boxes without spheres never retire.  The check runs on the device; the host
+ * reads one integer per check (the active boxes left) and stops when it is
+ * zero.  Full chunks are replayed as a captured HIP graph (check_every steps in
+ * `mode`, the forces and the check).  steady[nbox] (may be NULL) receives 1 for
+ * the boxes this call retired; stop_step[nbox] (may be NULL) the batch time
+ * (lbm_batch_time) at which each box stopped: its retiring check, the call's
+ * end for boxes still active, the call's start for boxes retired before.
+ * Host pointers; synchronises.  Errors: LBM_E_INVALID (max_steps < 0,
+ * check_every < 1, tol not positive and finite, another mode), LBM_E_HIP,
+ * LBM_E_STATE (a persistent wait hit its bound). */
+int lbm_batch_run_steady(lbm_batch *b, int64_t max_steps, double tol, int check_every, int mode,
+                         uint8_t *steady, int64_t *stop_step);
+
+/* Per-sphere drag data of the current state, spheres in box order (the
+ * closure's training and evaluation rows; "Simulation results" relates the
+ * drag to slip velocity and solid fraction).  F [total][3] binary64: the
+ * hydrodynamic force of the last step (as lbm_batch_forces).  feat
+ * [total][40] binary32, computed on the device in binary64 and rounded:
+ *   0      spheres other than this one with minimum-image centre distance
+ *          below 3R, over 27
+ *   1      log10 max(Re, 1e-6), Re = |U| 2R / nu, U the box's superficial
+ *          mean velocity (lbm_batch_mean_velocity), nu = (tau - 1/2) / 3
+ *   2..4   the shell velocity (lbm_batch_shell_velocity) over |U|, in the frame
+ *          e_x = U / |U|, e_y = e_x x z-hat normalised (e_x x y-hat when that
+ *          is shorter than 1e-8), e_z = e_x x e_y
+ *   5..36  the 16 nearest other spheres by distance (ties: lower index first),
+ *          each as (offset along e_x, distance across e_x) over 2R; slots
+ *          beyond the box's other spheres hold L / 2R
+ *   37     box solid fraction n (4/3) pi R^3 / L^3
+ *   38     2R / L
+ *   39     nearest surface gap (min distance - 2R) / 2R, or L / 2R for a
+ *          single sphere
+ * Either output may be NULL.  Synchronises.  Errors: LBM_E_INVALID (bad
+ * ptr_kind; feat requested with a box of more than 64 spheres), LBM_E_HIP. */
+int lbm_batch_get_drag(lbm_batch *b, double *F, float *feat, int ptr_kind);
+
 /* Boxes with active[b] == 0 are no longer advanced (retired). */
 int lbm_batch_set_active(lbm_batch *b, const uint8_t *active);
 

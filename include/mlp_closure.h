@@ -51,6 +51,21 @@ int mlp_get_params(mlp_ctx *ctx, float *params, int ptr_kind);
  * pointers, asynchronous on the context's stream). */
 int mlp_forward(mlp_ctx *ctx, const float *X, int64_t n, float *y);
 
+/* Input normalisation and training envelope for mlp_infer, 40 binary32 values
+ * each: a raw input x_k enters the network as (x_k - mu[k]) / sd[k]; a row is
+ * outside the envelope when some x_k < lo[k], x_k > hi[k] or is NaN.  Host or
+ * device pointers per ptr_kind.  Errors: LBM_E_INVALID (null pointer; for
+ * host input also sd[k] <= 0 or a non-finite mu or sd), LBM_E_HIP. */
+int mlp_set_normaliser(mlp_ctx *ctx, const float *mu, const float *sd, const float *lo,
+                       const float *hi, int ptr_kind);
+
+/* Inference on raw inputs with the fallback flag: y[n] = MLP((X - mu) / sd)
+ * with the current parameters, and out_of_envelope[n] (may be NULL) = 1 for
+ * the rows outside the training envelope, where the caller uses the resolved
+ * LB-IMB drag instead.  Device pointers, asynchronous on the context's stream.
+ * Errors: LBM_E_INVALID, LBM_E_STATE (no mlp_set_normaliser yet), LBM_E_HIP. */
+int mlp_infer(mlp_ctx *ctx, const float *X, int64_t n, float *y, uint8_t *out_of_envelope);
+
 /* Gradient of the mean squared error (1/n) sum (MLP(X) - y)^2 with respect to
  * every parameter, without updating them; grads[MLP_NPARAMS] and *loss are
  * written (device pointers for X, y; grads and loss follow ptr_kind). */

@@ -59,7 +59,8 @@ _SYMBOLS = ("lbm_workspace_bytes", "lbm_create", "lbm_destroy", "lbm_set_particl
             "mlp_forward", "mlp_gradients", "mlp_train_step", "mlp_gradients_noalloc",
             "lbm_batch_workspace_bytes", "lbm_batch_create", "lbm_batch_destroy", "lbm_batch_set_tile_rows",
             "lbm_batch_run", "lbm_batch_set_active", "lbm_batch_forces", "lbm_batch_mean_velocity",
-            "lbm_batch_get_distributions", "lbm_batch_autotune", "lbm_batch_time", "lbm_batch_shell_velocity")
+            "lbm_batch_get_distributions", "lbm_batch_autotune", "lbm_batch_time", "lbm_batch_shell_velocity",
+            "lbm_batch_run_steady", "lbm_batch_get_drag", "mlp_set_normaliser", "mlp_infer")
 
 
 def load():
@@ -339,7 +340,7 @@ def simulation_for(workload, storage="fp64", device="cuda:0", with_particles=Tru
     sim = Simulation(w.dim, w.shape, w.tau, storage=storage, wall_y=w.wall_y,
                      fluid_force=w.fluid_force, particle_accel=w.particle_accel,
                      samples=w.samples, kn=w.kn, restitution=w.restitution,
-                     max_particles=max(w.count, 1), device=device)
+                     max_particles=max(w.count, 1), max_radius=w.radius, device=device)
     if with_particles and w.count > 0:
         pos, vel, om, rad, rho, fixed = w.particles()
         sim.set_particles(pos, vel, om, rad, rho, fixed)
@@ -364,8 +365,10 @@ def _load_mlp(L):
     L.mlp_gradients.argtypes = [vp, vp, vp, i64, vp, vp, C.c_int]
     L.mlp_train_step.argtypes = [vp, vp, vp, i64, C.c_float, vp]
     L.mlp_gradients_noalloc.argtypes = [vp, vp, vp, i64, vp, vp, vp]
+    L.mlp_set_normaliser.argtypes = [vp, vp, vp, vp, vp, C.c_int]
+    L.mlp_infer.argtypes = [vp, vp, i64, vp, vp]
     for n in ("mlp_workspace_bytes", "mlp_create", "mlp_set_params", "mlp_get_params", "mlp_forward",
-              "mlp_gradients", "mlp_train_step", "mlp_gradients_noalloc"):
+              "mlp_gradients", "mlp_train_step", "mlp_gradients_noalloc", "mlp_set_normaliser", "mlp_infer"):
         getattr(L, n).restype = C.c_int
     L._mlp_ready = True
     return L
@@ -438,6 +441,25 @@ class Mlp:
             raise LbmError(rc, "mlp_forward")
         self._sync_out()
         return y
+
+    def set_normaliser(self, mu, sd, lo, hi):
+        a = [np.ascontiguousarray(np.asarray(v, dtype=np.float32).reshape(MLP_NIN)) for v in (mu, sd, lo, hi)]
+        rc = load().mlp_set_normaliser(self._ctx, *[_ptr(v) for v in a], LBM_HOST)
+        if rc:
+            raise LbmError(rc, "mlp_set_normaliser")
+
+    def infer(self, X):
+        """mlp_infer on raw inputs: (y [n] device tensor, out_of_envelope [n] device uint8 tensor)."""
+        X = self._dev(X, (-1, MLP_NIN))
+        n = X.shape[0]
+        y = self._torch.empty(n, dtype=self._torch.float32, device=self.device)
+        flag = self._torch.empty(n, dtype=self._torch.uint8, device=self.device)
+        self._sync_in()
+        rc = load().mlp_infer(self._ctx, _ptr(X), n, _ptr(y), _ptr(flag))
+        if rc:
+            raise LbmError(rc, "mlp_infer")
+        self._sync_out()
+        return y, flag
 
     def gradients(self, X, y):
         X = self._dev(X, (-1, MLP_NIN))
@@ -533,9 +555,12 @@ def _load_batch(L):
     L.lbm_batch_autotune.argtypes = [vp, C.c_int, vp, vp, vp, vp]
     L.lbm_batch_time.argtypes = [vp]
     L.lbm_batch_time.restype = i64
+    L.lbm_batch_run_steady.argtypes = [vp, i64, C.c_double, C.c_int, C.c_int, vp, vp]
+    L.lbm_batch_get_drag.argtypes = [vp, vp, vp, C.c_int]
     for n in ("lbm_batch_workspace_bytes", "lbm_batch_create", "lbm_batch_set_tile_rows", "lbm_batch_run",
               "lbm_batch_set_active", "lbm_batch_forces", "lbm_batch_mean_velocity",
-              "lbm_batch_shell_velocity", "lbm_batch_get_distributions", "lbm_batch_autotune"):
+              "lbm_batch_shell_velocity", "lbm_batch_get_distributions", "lbm_batch_autotune",
+              "lbm_batch_run_steady", "lbm_batch_get_drag"):
         getattr(L, n).restype = C.c_int
     L._batch_ready = True
     return L
@@ -612,6 +637,23 @@ class Batch:
 
     def run(self, nsteps, mode=LBM_BATCH_PER_STEP):
         self._chk(load().lbm_batch_run(self._ctx, int(nsteps), int(mode)), "lbm_batch_run")
+
+    def run_steady(self, max_steps, tol, check_every, mode=LBM_BATCH_PER_STEP):
+        """lbm_batch_run_steady: returns (steady [nbox] bool, stop_step [nbox])."""
+        st = np.zeros(self.nbox, dtype=np.uint8)
+        stop = np.zeros(self.nbox, dtype=np.int64)
+        self._chk(load().lbm_batch_run_steady(self._ctx, int(max_steps), float(tol), int(check_every), int(mode),
+                                              _ptr(st), _ptr(stop)), "lbm_batch_run_steady")
+        return st.astype(bool), stop
+
+    def get_drag(self, features=True):
+        """lbm_batch_get_drag: (F [nsph, 3] binary64, X [nsph, 40] binary32 or None)."""
+        n = max(self.nsph, 1)
+        F = np.zeros((n, 3))
+        X = np.zeros((n, 40), dtype=np.float32) if features else None
+        if self.nsph:
+            self._chk(load().lbm_batch_get_drag(self._ctx, _ptr(F), _ptr(X), LBM_HOST), "lbm_batch_get_drag")
+        return F[: self.nsph], (X[: self.nsph] if features else None)
 
     def set_active(self, active):
         a = np.ascontiguousarray(np.asarray(active, dtype=np.uint8).reshape(self.nbox))

@@ -332,6 +332,160 @@ hipError_t launch_batch_shell(const BatchArgs &a, int parity, double *u, hipStre
     return hipGetLastError();
 }
 
+// Steady-drag check after a chunk of steps, on the device: one workgroup,
+// thread k takes the boxes k, k + 256, ...  An active box with spheres
+// retires when max over its spheres and components of |F - F_prev| is below
+// tol times the mean over its spheres of |F| (both from the force kernel of
+// the chunk's last step); the first check of a run only records F_prev.
+// Boxes without spheres never retire.  Each box's sums run in sphere order,
+// so the decision is reproducible.  The check time and the first-check flag
+// live on the device (*st.tnow advances by the chunk's k steps), so one
+// captured chunk serves every replay.  *remaining receives the active boxes
+// left.
+__global__ __launch_bounds__(256) void k_batch_check(BatchArgs a, BatchBox *boxes, BatchSteady st, int64_t k) {
+    __shared__ int live[256];
+    const int64_t t = *st.tnow + k;
+    const int first = *st.first;
+    int n_live = 0;
+    for (int b = threadIdx.x; b < a.nbox; b += blockDim.x) {
+        if (!boxes[b].active) continue;
+        const int p0 = boxes[b].sph0, np = boxes[b].nsph;
+        bool retire = false;
+        if (!first && np > 0) {
+            double scale = 0.0, dmax = 0.0;
+            for (int p = p0; p < p0 + np; p++) {
+                const double f0 = a.F[3 * p], f1 = a.F[3 * p + 1], f2 = a.F[3 * p + 2];
+                scale = scale + sqrt(f0 * f0 + f1 * f1 + f2 * f2);
+                for (int d = 0; d < 3; d++) dmax = fmax(dmax, fabs(a.F[3 * p + d] - st.Fprev[3 * p + d]));
+            }
+            scale = scale / (double)np;
+            retire = scale > 0.0 && dmax / scale < st.tol;
+        }
+        for (int p = p0; p < p0 + np; p++)
+            for (int d = 0; d < 3; d++) st.Fprev[3 * p + d] = a.F[3 * p + d];
+        if (retire) {
+            boxes[b].active = 0;
+            st.steady[b] = 1;
+            st.stop[b] = t;
+        } else {
+            n_live++;
+        }
+    }
+    live[threadIdx.x] = n_live;
+    __syncthreads();
+    for (int k = blockDim.x / 2; k > 0; k >>= 1) {
+        if ((int)threadIdx.x < k) live[threadIdx.x] += live[threadIdx.x + k];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {  // every thread read *tnow and *first before the barriers above
+        *st.remaining = live[0];
+        *st.tnow = t;
+        *st.first = 0;
+    }
+}
+
+hipError_t launch_batch_check(const BatchArgs &a, BatchBox *boxes, const BatchSteady &st, int64_t k,
+                              hipStream_t s) {
+    hipLaunchKernelGGL(k_batch_check, dim3(1), dim3(256), 0, s, a, boxes, st, k);
+    return hipGetLastError();
+}
+
+// The 40 closure inputs of every sphere, binary32 [nsph][40]; one wavefront
+// per sphere, lane j holding sphere j of the same box (at most 64 per box).
+//   0      local solid fraction: spheres other than this one whose
+//          minimum-image centre distance is below 3R, over 27
+//   1      log10 of max(Re, 1e-6), Re = |U| d / nu, U the box's superficial
+//          mean velocity, d = 2R, nu = (tau - 1/2) / 3
+//   2..4   shell velocity Us of the sphere over |U| in the flow frame
+//          (e_x = U / |U|; e_y = e_x x z-hat normalised, or e_x x y-hat when
+//          that is shorter than 1e-8; e_z = e_x x e_y)
+//   5..36  the 16 nearest other spheres (distance, then index), each as its
+//          offset along e_x over d and its distance across e_x over d; the
+//          slots beyond the box's other spheres hold L / d
+//   37     box solid fraction n (4/3) pi R^3 / L^3
+//   38     d / L
+//   39     nearest surface gap (min distance - d) / d, or L / d alone in a box
+// Arithmetic is binary64, rounded to binary32 at the store.
+__global__ __launch_bounds__(256) void k_batch_features(BatchArgs a, const double *U, const double *Us,
+                                                        float *feat) {
+    const int lane = threadIdx.x & 63;
+    const int p = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (p >= a.nsph) return;
+    const int b = a.sph_box[p];
+    const BatchBox bx = a.boxes[b];
+    const int n = bx.nsph, me = p - bx.sph0;
+    const double R = bx.radius, Ld = (double)bx.L, d = 2.0 * R, nu = (bx.tau - 0.5) / 3.0;
+    const double u0 = U[3 * b], u1 = U[3 * b + 1], u2 = U[3 * b + 2];
+    const double umag = sqrt(u0 * u0 + u1 * u1 + u2 * u2);
+    const double re = umag * d / nu;
+    double ex[3] = {1.0, 0.0, 0.0};
+    if (umag > 0.0) {
+        ex[0] = u0 / umag;
+        ex[1] = u1 / umag;
+        ex[2] = u2 / umag;
+    }
+    const bool other = lane < n && lane != me;
+    double dv[3] = {0.0, 0.0, 0.0}, dist = INFINITY;
+    if (other) {
+        const int j = bx.sph0 + lane;
+        for (int k = 0; k < 3; k++) {
+            const double v = a.sph_x[3 * j + k] - a.sph_x[3 * p + k];
+            dv[k] = v - Ld * rint(v / Ld);
+        }
+        dist = sqrt(dv[0] * dv[0] + dv[1] * dv[1] + dv[2] * dv[2]);
+    }
+    int rank = 0;
+    double dmin = dist;
+    for (int k = 0; k < 64; k++) {
+        const double dk = __shfl(dist, k, 64);
+        rank += (dk < dist || (dk == dist && k < lane)) ? 1 : 0;
+        dmin = fmin(dmin, dk);
+    }
+    const int n_loc = __popcll(__ballot(other && dist < 3.0 * R));
+    float *row = feat + (int64_t)40 * p;
+    if (other && rank < 16) {
+        const double along = dv[0] * ex[0] + dv[1] * ex[1] + dv[2] * ex[2];
+        const double across = sqrt(fmax(dist * dist - along * along, 0.0));
+        row[5 + 2 * rank] = (float)(along / d);
+        row[6 + 2 * rank] = (float)(across / d);
+    }
+    if (lane >= n - 1 && lane < 16) {  // slots beyond the other spheres
+        row[5 + 2 * lane] = (float)(Ld / d);
+        row[6 + 2 * lane] = (float)(Ld / d);
+    }
+    if (lane == 0) {
+        double ey[3] = {ex[1], -ex[0], 0.0};  // e_x x z-hat
+        double ny = sqrt(ey[0] * ey[0] + ey[1] * ey[1] + ey[2] * ey[2]);
+        if (ny < 1e-8) {  // e_x x y-hat
+            ey[0] = -ex[2];
+            ey[1] = 0.0;
+            ey[2] = ex[0];
+            ny = sqrt(ey[0] * ey[0] + ey[1] * ey[1] + ey[2] * ey[2]);
+        }
+        for (int k = 0; k < 3; k++) ey[k] = ey[k] / ny;
+        const double ez[3] = {ex[1] * ey[2] - ex[2] * ey[1], ex[2] * ey[0] - ex[0] * ey[2],
+                              ex[0] * ey[1] - ex[1] * ey[0]};
+        const double um = fmax(umag, 1e-300);
+        const double us[3] = {Us[3 * p] / um, Us[3 * p + 1] / um, Us[3 * p + 2] / um};
+        row[0] = (float)((double)n_loc / 27.0);
+        row[1] = (float)log10(fmax(re, 1e-6));
+        row[2] = (float)(us[0] * ex[0] + us[1] * ex[1] + us[2] * ex[2]);
+        row[3] = (float)(us[0] * ey[0] + us[1] * ey[1] + us[2] * ey[2]);
+        row[4] = (float)(us[0] * ez[0] + us[1] * ez[1] + us[2] * ez[2]);
+        const double vol = 4.0 / 3.0 * M_PI * R * R * R;
+        row[37] = (float)((double)n * vol / (Ld * Ld * Ld));
+        row[38] = (float)(d / Ld);
+        row[39] = (float)(n > 1 ? (dmin - d) / d : Ld / d);
+    }
+}
+
+hipError_t launch_batch_features(const BatchArgs &a, const double *U, const double *Us, float *feat,
+                                 hipStream_t s) {
+    if (a.nsph == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_batch_features, dim3((unsigned)((a.nsph + 3) / 4)), dim3(256), 0, s, a, U, Us, feat);
+    return hipGetLastError();
+}
+
 int batch_persistent_grid() {
     int dev = 0, cus = 0, per = 0;
     if (hipGetDevice(&dev) != hipSuccess) return 1024;

@@ -26,7 +26,7 @@ struct BLayout {
     int nbox, nsph, Smax, ntiles;
     int64_t total_nodes, pool, list_total;
     size_t A, B, cnt, q, beta, arel, boxes, tile_box, queue, done, flags, sph_box, sph_x, lstart, list, F,
-        T, U, total;
+        T, U, Fprev, steady, stop, misc, Us, feat, total;
 };
 
 double pdisp(double d, double L) {
@@ -111,6 +111,12 @@ BLayout make_blayout(const lbm_box *boxes, int nbox, int S, int64_t list_total) 
     L.F = take((size_t)std::max(nsph, 1) * 24);
     L.T = take((size_t)std::max(nsph, 1) * 24);
     L.U = take((size_t)nbox * 24);
+    L.Fprev = take((size_t)std::max(nsph, 1) * 24);
+    L.steady = take((size_t)nbox * 4);
+    L.stop = take((size_t)nbox * 8);
+    L.misc = take(64);  // remaining (int), first check (int), check time (int64)
+    L.Us = take((size_t)std::max(nsph, 1) * 24);
+    L.feat = take((size_t)std::max(nsph, 1) * 40 * 4);
     L.total = o;
     return L;
 }
@@ -175,6 +181,12 @@ struct lbm_batch {
     BLayout L;
     char *ws;
     hipStream_t s;
+    hipStream_t cap;              // private stream the steady-run chunks are captured on
+    hipGraphExec_t chunk[2];      // captured chunk (check_every steps, forces, check) per starting parity
+    bool chunk_ok[2];
+    int64_t chunk_k;              // steps, mode and tolerance the captured chunks hold
+    int chunk_mode;
+    double chunk_tol;
     std::vector<BatchBox> box;
     std::vector<int> tile_box;
     int ntiles;
@@ -214,8 +226,28 @@ BatchArgs bargs(lbm_batch *c) {
     return a;
 }
 
+BatchSteady steady_args(lbm_batch *c, double tol) {
+    BatchSteady st;
+    st.Fprev = Pp<double>(c, c->L.Fprev);
+    st.steady = Pp<int>(c, c->L.steady);
+    st.stop = Pp<int64_t>(c, c->L.stop);
+    st.remaining = Pp<int>(c, c->L.misc);
+    st.first = Pp<int>(c, c->L.misc + 4);
+    st.tnow = Pp<int64_t>(c, c->L.misc + 8);
+    st.tol = tol;
+    return st;
+}
+
+void drop_chunks(lbm_batch *c) {
+    for (int k = 0; k < 2; k++) {
+        if (c->chunk_ok[k]) (void)hipGraphExecDestroy(c->chunk[k]);
+        c->chunk_ok[k] = false;
+    }
+}
+
 // Rebuild tile numbering after a tile-shape change and upload descriptors.
 hipError_t upload_tiles(lbm_batch *c) {
+    drop_chunks(c);  // captured launches hold the tile count
     c->tile_box.clear();
     int t = 0;
     for (int b = 0; b < c->L.nbox; b++) {
@@ -245,34 +277,71 @@ hipError_t reset_state(lbm_batch *c) {
     return e;
 }
 
-int run_steps(lbm_batch *c, int64_t nsteps, int mode) {
+// Queue nsteps steps starting from state `from` on stream s (no wait).
+hipError_t enqueue_steps(lbm_batch *c, int64_t nsteps, int mode, int from, hipStream_t s) {
     BatchArgs a = bargs(c);
     hipError_t e = hipSuccess;
+    int cur = from;
     if (mode == LBM_BATCH_PERSISTENT) {
         // items are counted in a 32-bit integer: keep nsteps * ntiles (plus one
         // overshoot per workgroup) far below 2^31
         const int chunk = std::max(1, (int)(((int64_t)1 << 30) / std::max(c->ntiles, 1)));
         for (int64_t done = 0; done < nsteps && e == hipSuccess;) {
             const int k = (int)std::min<int64_t>(nsteps - done, chunk);
-            e = launch_fill_u32((uint32_t *)a.queue, 0u, 1, c->s);
-            if (e == hipSuccess) e = launch_fill_u32((uint32_t *)a.done, 0u, c->L.nbox, c->s);
-            if (e == hipSuccess) e = launch_batch_persistent(a, k, c->cur, c->pgrid, c->s);
-            c->cur = (c->cur + k) & 1;
+            e = launch_fill_u32((uint32_t *)a.queue, 0u, 1, s);
+            if (e == hipSuccess) e = launch_fill_u32((uint32_t *)a.done, 0u, c->L.nbox, s);
+            if (e == hipSuccess) e = launch_batch_persistent(a, k, cur, c->pgrid, s);
+            cur = (cur + k) & 1;
             done += k;
         }
     } else {
         for (int64_t k = 0; k < nsteps && e == hipSuccess; k++) {
-            e = launch_batch_step(a, c->cur, c->s);
-            c->cur ^= 1;
+            e = launch_batch_step(a, cur, s);
+            cur ^= 1;
         }
     }
-    c->t += nsteps;
-    if (e != hipSuccess) return LBM_E_HIP;
+    return e;
+}
+
+// Health word of the batch (synchronises).
+int read_flags(lbm_batch *c) {
     uint32_t h = 0;
-    if (hipMemcpyAsync(&h, a.flags, 4, hipMemcpyDeviceToHost, c->s) != hipSuccess) return LBM_E_HIP;
+    if (hipMemcpyAsync(&h, Pp<uint32_t>(c, c->L.flags), 4, hipMemcpyDeviceToHost, c->s) != hipSuccess)
+        return LBM_E_HIP;
     if (hipStreamSynchronize(c->s) != hipSuccess) return LBM_E_HIP;
     if (h & FLAG_BATCH_TIMEOUT) return LBM_E_STATE;
     return LBM_OK;
+}
+
+int run_steps(lbm_batch *c, int64_t nsteps, int mode) {
+    hipError_t e = enqueue_steps(c, nsteps, mode, c->cur, c->s);
+    c->cur = (int)((c->cur + nsteps) & 1);
+    c->t += nsteps;
+    if (e != hipSuccess) return LBM_E_HIP;
+    return read_flags(c);
+}
+
+// One chunk of a steady run: k steps from state `from`, the forces of the
+// last step and the device-side steady check.
+hipError_t enqueue_chunk(lbm_batch *c, int64_t k, int mode, int from, double tol, hipStream_t s) {
+    hipError_t e = enqueue_steps(c, k, mode, from, s);
+    if (e == hipSuccess) e = launch_batch_force(bargs(c), s);
+    if (e == hipSuccess) e = launch_batch_check(bargs(c), Pp<BatchBox>(c, c->L.boxes), steady_args(c, tol), k, s);
+    return e;
+}
+
+hipError_t build_chunk(lbm_batch *c, int64_t k, int mode, int from, double tol) {
+    hipGraph_t g;
+    hipError_t e = hipStreamBeginCapture(c->cap, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return e;
+    const hipError_t e1 = enqueue_chunk(c, k, mode, from, tol, c->cap);
+    const hipError_t e2 = hipStreamEndCapture(c->cap, &g);
+    if (e1 != hipSuccess) return e1;
+    if (e2 != hipSuccess) return e2;
+    e = hipGraphInstantiate(&c->chunk[from], g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e == hipSuccess) c->chunk_ok[from] = true;
+    return e;
 }
 }  // namespace
 
@@ -305,6 +374,14 @@ int lbm_batch_create(const lbm_box *boxes, int nbox, int eps_samples, void *work
     c->s = (hipStream_t)hip_stream;
     c->pgrid = batch_persistent_grid();
     c->mode_hint = LBM_BATCH_PER_STEP;
+    c->chunk_ok[0] = c->chunk_ok[1] = false;
+    c->chunk_k = 0;
+    c->chunk_mode = -1;
+    c->chunk_tol = 0.0;
+    if (hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking) != hipSuccess) {
+        delete c;
+        return LBM_E_HIP;
+    }
     // per-box descriptors and tables
     const int S1 = L.Smax + 1;
     std::vector<float> beta((size_t)nbox * S1), arel((size_t)nbox * S1);
@@ -322,6 +399,9 @@ int lbm_batch_create(const lbm_box *boxes, int nbox, int eps_samples, void *work
         d.noff = noff;
         d.table = b * S1;
         d.active = 1;
+        d.tau = x.tau;
+        d.sph0 = (int)sph_box.size();
+        d.nsph = x.nspheres;
         const double tau = x.tau;
         d.arel0f = (float)((1.0 - 0.0) / tau);
         for (int i = 0; i < 19; i++) {
@@ -368,6 +448,8 @@ int lbm_batch_create(const lbm_box *boxes, int nbox, int eps_samples, void *work
     if (e == hipSuccess) e = reset_state(c);
     if (e == hipSuccess) e = hipStreamSynchronize(c->s);
     if (e != hipSuccess) {
+        drop_chunks(c);
+        (void)hipStreamDestroy(c->cap);
         delete c;
         return LBM_E_HIP;
     }
@@ -378,6 +460,8 @@ int lbm_batch_create(const lbm_box *boxes, int nbox, int eps_samples, void *work
 void lbm_batch_destroy(lbm_batch *c) {
     if (!c) return;
     (void)hipStreamSynchronize(c->s);
+    drop_chunks(c);
+    (void)hipStreamDestroy(c->cap);
     delete c;
 }
 
@@ -451,6 +535,80 @@ int lbm_batch_get_distributions(lbm_batch *c, int b, double *f, int ptr_kind) {
     if (e == hipSuccess) e = hipStreamSynchronize(c->s);
     if (ptr_kind == LBM_HOST) (void)hipFree(dst);
     return e == hipSuccess ? LBM_OK : LBM_E_HIP;
+}
+
+int lbm_batch_run_steady(lbm_batch *c, int64_t max_steps, double tol, int check_every, int mode,
+                         uint8_t *steady, int64_t *stop_step) {
+    if (!c || max_steps < 0 || check_every < 1 || !(tol > 0.0) || !std::isfinite(tol) ||
+        (mode != LBM_BATCH_PER_STEP && mode != LBM_BATCH_PERSISTENT))
+        return LBM_E_INVALID;
+    const int nb = c->L.nbox;
+    const int64_t t0 = c->t;
+    BatchSteady st = steady_args(c, tol);
+    hipError_t e = launch_fill_u32((uint32_t *)st.steady, 0u, nb, c->s);
+    if (e == hipSuccess) e = launch_fill_u64((uint64_t *)st.stop, (uint64_t)t0, nb, c->s);
+    if (e == hipSuccess) e = launch_fill_u32((uint32_t *)st.first, 1u, 1, c->s);
+    if (e == hipSuccess) e = launch_fill_u64((uint64_t *)st.tnow, (uint64_t)t0, 1, c->s);
+    if (e != hipSuccess) return LBM_E_HIP;
+    if (c->chunk_k != check_every || c->chunk_mode != mode || c->chunk_tol != tol) {
+        drop_chunks(c);
+        c->chunk_k = check_every;
+        c->chunk_mode = mode;
+        c->chunk_tol = tol;
+    }
+    std::vector<uint8_t> was_active(nb);
+    int left = 0;
+    for (int b = 0; b < nb; b++) left += (was_active[b] = (uint8_t)c->box[b].active);
+    int64_t done = 0;
+    while (done < max_steps && left > 0) {
+        const int64_t k = std::min<int64_t>(check_every, max_steps - done);
+        if (k == check_every) {
+            if (!c->chunk_ok[c->cur] && build_chunk(c, k, mode, c->cur, tol) != hipSuccess) return LBM_E_HIP;
+            if (hipGraphLaunch(c->chunk[c->cur], c->s) != hipSuccess) return LBM_E_HIP;
+        } else if (enqueue_chunk(c, k, mode, c->cur, tol, c->s) != hipSuccess) {
+            return LBM_E_HIP;
+        }
+        c->cur = (int)((c->cur + k) & 1);
+        c->t += k;
+        done += k;
+        if (hipMemcpyAsync(&left, st.remaining, 4, hipMemcpyDeviceToHost, c->s) != hipSuccess) return LBM_E_HIP;
+        const int rc = read_flags(c);  // synchronises
+        if (rc != LBM_OK) return rc;
+    }
+    std::vector<int> st_h(nb);
+    std::vector<int64_t> stop_h(nb);
+    if (hipMemcpyAsync(st_h.data(), st.steady, (size_t)nb * 4, hipMemcpyDeviceToHost, c->s) != hipSuccess ||
+        hipMemcpyAsync(stop_h.data(), st.stop, (size_t)nb * 8, hipMemcpyDeviceToHost, c->s) != hipSuccess ||
+        hipStreamSynchronize(c->s) != hipSuccess)
+        return LBM_E_HIP;
+    for (int b = 0; b < nb; b++) {
+        if (st_h[b]) c->box[b].active = 0;  // the device descriptor was cleared by the check
+        else if (was_active[b]) stop_h[b] = c->t;
+        if (steady) steady[b] = (uint8_t)(st_h[b] ? 1 : 0);
+        if (stop_step) stop_step[b] = stop_h[b];
+    }
+    return LBM_OK;
+}
+
+int lbm_batch_get_drag(lbm_batch *c, double *F, float *feat, int ptr_kind) {
+    if (!c || (ptr_kind != LBM_HOST && ptr_kind != LBM_DEVICE)) return LBM_E_INVALID;
+    const int nsph = c->L.nsph;
+    if (nsph == 0) return LBM_OK;
+    const hipMemcpyKind k = ptr_kind == LBM_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice;
+    if (F && hipMemcpyAsync(F, c->ws + c->L.F, (size_t)nsph * 24, k, c->s) != hipSuccess) return LBM_E_HIP;
+    if (feat) {
+        for (auto &x : c->box)
+            if (x.nsph > 64) return LBM_E_INVALID;
+        BatchArgs a = bargs(c);
+        double *U = Pp<double>(c, c->L.U), *Us = Pp<double>(c, c->L.Us);
+        float *X = Pp<float>(c, c->L.feat);
+        hipError_t e = launch_batch_mean(a, c->cur, U, c->s);
+        if (e == hipSuccess) e = launch_batch_shell(a, c->cur, Us, c->s);
+        if (e == hipSuccess) e = launch_batch_features(a, U, Us, X, c->s);
+        if (e == hipSuccess) e = hipMemcpyAsync(feat, X, (size_t)nsph * 160, k, c->s);
+        if (e != hipSuccess) return LBM_E_HIP;
+    }
+    return hipStreamSynchronize(c->s) == hipSuccess ? LBM_OK : LBM_E_HIP;
 }
 
 int64_t lbm_batch_time(const lbm_batch *c) { return c ? c->t : -1; }

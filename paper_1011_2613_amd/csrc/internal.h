@@ -194,6 +194,20 @@ struct BatchBox {
     float cgf[19];         // c_i . g_fluid
     float g0[19];          // initial shifted populations f^eq_i(1, u0) - w_i
     double radius;         // sphere radius of the box
+    double tau;            // relaxation time
+    int sph0;              // first sphere of the box (global sphere index)
+    int nsph;              // spheres in the box
+};
+
+// State of the steady-drag check of lbm_batch_run_steady.
+struct BatchSteady {
+    double *Fprev;         // [nsph][3] force at the previous check
+    int *steady;           // [nbox] 1: retired by the check
+    int64_t *stop;         // [nbox] batch time at which the box retired
+    int *remaining;        // active boxes after the last check
+    int *first;            // 1: the next check only records F_prev (cleared by the check)
+    int64_t *tnow;         // batch time of the last check (advanced by the check)
+    double tol;
 };
 
 struct BatchArgs {
@@ -225,6 +239,10 @@ hipError_t launch_batch_mean(const BatchArgs &a, int parity, double *U, hipStrea
 hipError_t launch_batch_get_f(const BatchArgs &a, int b, int L, int parity, double *f, hipStream_t s);
 hipError_t launch_batch_init(const BatchArgs &a, int nbox, int maxL, hipStream_t s);
 hipError_t launch_batch_shell(const BatchArgs &a, int parity, double *u, hipStream_t s);
+hipError_t launch_batch_check(const BatchArgs &a, BatchBox *boxes, const BatchSteady &st, int64_t k,
+                              hipStream_t s);
+hipError_t launch_batch_features(const BatchArgs &a, const double *U, const double *Us, float *feat,
+                                 hipStream_t s);
 int batch_persistent_grid();
 
 // launchers (lb_kernels.hip)

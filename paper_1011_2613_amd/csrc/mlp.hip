@@ -22,6 +22,7 @@
 #include <math.h>
 
 #include <algorithm>
+#include <cmath>
 #include <mutex>
 #include <new>
 
@@ -72,6 +73,8 @@ __device__ __forceinline__ float dsilu(float z) {
 
 struct FwdArgs {
     const float *X;      // [n][40]
+    const float *nmu;    // inputs enter as (X - nmu) / nsd when not null
+    const float *nsd;
     int64_t n;
     const float *p;      // master parameters (biases read from here)
     Wbf w;
@@ -156,7 +159,9 @@ __global__ __launch_bounds__(TRAIN ? 64 * FWD_WAVES_TRAIN : 64 * FWD_WAVES) void
 #pragma unroll
         for (int j = 0; j < XL; j++) {
             const int idx = j * 64 + l, r = idx / NIN, k = idx % NIN;
-            const __bf16 q = (__bf16)xv[j];
+            float xk = xv[j];
+            if (!TRAIN && a.nmu && r0 + r < a.n) xk = (xk - a.nmu[k]) / a.nsd[k];
+            const __bf16 q = (__bf16)xk;
             buf[r * S1 + k] = q;
             if (TRAIN && r0 + r < a.n) a.h0[(r0 + r) * KIN + k] = q;
         }
@@ -356,13 +361,25 @@ __global__ void k_pack(const float *p, Wbf w) {
     if (i < 16 * NH) w.w4[i] = (__bf16)(i < NH ? p[OFF_W4 + i] : 0.0f);
 }
 
+// out[r] = 1 when some input of row r lies outside [lo, hi] (or is NaN).
+__global__ void k_envelope(const float *X, int64_t n, const float *lo, const float *hi, uint8_t *out) {
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= n) return;
+    bool inside = true;
+    for (int k = 0; k < NIN; k++) {
+        const float x = X[r * NIN + k];
+        inside = inside && x >= lo[k] && x <= hi[k];
+    }
+    out[r] = inside ? 0 : 1;
+}
+
 constexpr size_t AL = 256;
 constexpr size_t al(size_t v) { return (v + AL - 1) / AL * AL; }
 
 struct Lay {
     int64_t B;  // batch capacity, multiple of 32
     size_t p, m, v, g, w1, w2, w3, w4, h0, h1, h2, h3, z1, z2, z3, y, gout, gq, sq, dz, dzq, dh,
-        tmp, loss, total;
+        tmp, loss, norm, total;
 };
 
 // masters: whether the binary32 parameters, their gradient and the Adam
@@ -382,6 +399,7 @@ constexpr Lay layout(int64_t max_batch, bool masters = true) {
     L.y = take(B * 4); L.gout = take(B * 4); L.gq = take(B * 2); L.sq = take(B * 4);
     L.dz = take(B * NH * 4); L.dzq = take(B * NH * 2); L.dh = take(B * NH * 4);
     L.tmp = take(NH * KIN * 4); L.loss = take(64);
+    L.norm = masters ? take(4 * NIN * 4) : 0;
     L.total = o;
     return L;
 }
@@ -394,6 +412,7 @@ struct mlp_ctx {
     hipStream_t s;
     int t;
     Wbf w;
+    bool have_norm;  // mlp_set_normaliser was called
 };
 
 namespace {
@@ -447,7 +466,7 @@ hipError_t grads(const GradBufs &b, const float *X, const float *y, int64_t n) {
                 return e;
         }
     }
-    FwdArgs fa;
+    FwdArgs fa{};
     fa.X = X; fa.n = n; fa.p = b.p; fa.w = b.w; fa.y = Q<float>(b, L.y);
     fa.h0 = Q<__bf16>(b, L.h0); fa.h1 = Q<__bf16>(b, L.h1); fa.h2 = Q<__bf16>(b, L.h2);
     fa.h3 = Q<__bf16>(b, L.h3);
@@ -549,6 +568,7 @@ int mlp_create(int64_t max_batch, void *workspace, size_t ws_bytes, void *hip_st
     c->ws = (char *)workspace;
     c->s = (hipStream_t)hip_stream;
     c->t = 0;
+    c->have_norm = false;
     c->w.w1 = P<__bf16>(c, L.w1);
     c->w.w2 = P<__bf16>(c, L.w2);
     c->w.w3 = P<__bf16>(c, L.w3);
@@ -594,6 +614,38 @@ int mlp_forward(mlp_ctx *c, const float *X, int64_t n, float *y) {
     const int64_t tiles = (n + 15) / 16;
     const unsigned blocks = (unsigned)std::min<int64_t>((tiles + FWD_WAVES - 1) / FWD_WAVES, 1024);
     hipLaunchKernelGGL(k_mlp_forward<false>, dim3(blocks), dim3(64 * FWD_WAVES), 0, c->s, fa);
+    return hipGetLastError() == hipSuccess ? LBM_OK : LBM_E_HIP;
+}
+
+int mlp_set_normaliser(mlp_ctx *c, const float *mu, const float *sd, const float *lo, const float *hi,
+                       int ptr_kind) {
+    if (!c || !mu || !sd || !lo || !hi || (ptr_kind != LBM_HOST && ptr_kind != LBM_DEVICE)) return LBM_E_INVALID;
+    if (ptr_kind == LBM_HOST)
+        for (int k = 0; k < NIN; k++)
+            if (!(sd[k] > 0.0f) || !std::isfinite(sd[k]) || !std::isfinite(mu[k])) return LBM_E_INVALID;
+    const hipMemcpyKind kind = ptr_kind == LBM_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice;
+    const float *src[4] = {mu, sd, lo, hi};
+    for (int j = 0; j < 4; j++)
+        if (hipMemcpyAsync(P<float>(c, c->L.norm) + j * NIN, src[j], NIN * 4, kind, c->s) != hipSuccess)
+            return LBM_E_HIP;
+    if (ptr_kind == LBM_HOST && hipStreamSynchronize(c->s) != hipSuccess) return LBM_E_HIP;
+    c->have_norm = true;
+    return LBM_OK;
+}
+
+int mlp_infer(mlp_ctx *c, const float *X, int64_t n, float *y, uint8_t *out_of_envelope) {
+    if (!c || !X || !y || n < 0) return LBM_E_INVALID;
+    if (!c->have_norm) return LBM_E_STATE;
+    if (n == 0) return LBM_OK;
+    const float *nb = P<float>(c, c->L.norm);
+    FwdArgs fa{};
+    fa.X = X; fa.nmu = nb; fa.nsd = nb + NIN; fa.n = n; fa.p = P<float>(c, c->L.p); fa.w = c->w; fa.y = y;
+    const int64_t tiles = (n + 15) / 16;
+    const unsigned blocks = (unsigned)std::min<int64_t>((tiles + FWD_WAVES - 1) / FWD_WAVES, 1024);
+    hipLaunchKernelGGL(k_mlp_forward<false>, dim3(blocks), dim3(64 * FWD_WAVES), 0, c->s, fa);
+    if (out_of_envelope)
+        hipLaunchKernelGGL(k_envelope, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c->s, X, n, nb + 2 * NIN,
+                           nb + 3 * NIN, out_of_envelope);
     return hipGetLastError() == hipSuccess ? LBM_OK : LBM_E_HIP;
 }
 

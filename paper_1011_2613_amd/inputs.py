@@ -241,6 +241,12 @@ def workload(name):
         density ratio 692.3, gravity 4.704e-7 along -y on the particles and
         the body force 4.04e-5 along +y on the fluid that balances it,
         k = 17892, e = 0.9, initial particle speed 5e-3, 4^3 sampling.
+    P2  The paper's 2D suspension at full size (simulation section, Table 2
+        2D column): D2Q9 15360x61440 periodic on both axes, 1,166,400 discs
+        d = 10 (solid fraction 0.097), nu 0.1231 (tau 0.8693), density ratio
+        692.3, gravity 1.176e-7 along -y on the particles and the body force
+        8.753e-6 along +y on the fluid that balances it, k = 2686, e = 0.9,
+        initial particle speed 5e-3, 8x8 sampling.
     """
     if name == "C1":
         return Workload("C1", 2, (256, 256), 0.6, False, 6.0, 16, 10.0, 8, 1.0e3, 0.9, 1000,
@@ -267,5 +273,10 @@ def workload(name):
         nu, rr, g = 0.2462, 692.3, 4.704e-7
         return Workload("P3", 3, (512, 2016, 512), 0.5 + 3.0 * nu, False, 5.0, 129024, rr, 4,
                         17892.0, 0.9, 2000, seed=4, v0=5.0e-3, fluid_force=(0.0, 4.04e-5, 0.0),
+                        particle_accel=(0.0, -(1.0 - 1.0 / rr) * g, 0.0))
+    if name == "P2":
+        nu, rr, g = 0.1231, 692.3, 1.176e-7
+        return Workload("P2", 2, (15360, 61440), 0.5 + 3.0 * nu, False, 5.0, 1166400, rr, 8,
+                        2686.0, 0.9, 2000, seed=5, v0=5.0e-3, fluid_force=(0.0, 8.753e-6, 0.0),
                         particle_accel=(0.0, -(1.0 - 1.0 / rr) * g, 0.0))
     raise KeyError(name)

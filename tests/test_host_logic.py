@@ -1,5 +1,6 @@
-"""Host-side logic of the package that needs no GPU: the resolution study's
-extrapolation and the closure's input features."""
+"""Host-side logic that needs no GPU: the resolution study's extrapolation
+and the numpy reference of the closure's input features (the check of the
+device feature kernel)."""
 import numpy as np
 
 
@@ -21,7 +22,7 @@ def test_closure_neighbour_features():
     and across it over d (minimum image), padded with L/d when the box holds
     fewer spheres; the other inputs sit where the evaluation expects them."""
     import math
-    from paper_1011_2613_amd import ensemble as E
+    import closure_features_ref as E
     L, R = 32, 2.0
     d = 2 * R
     pos = np.array([[5.0, 5.0, 5.0], [9.0, 5.0, 5.0], [5.0, 11.0, 5.0], [30.0, 5.0, 8.0]])

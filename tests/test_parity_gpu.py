@@ -432,64 +432,98 @@ def test_full_size_first_steps(gpu_lib, name, steps):
 
 
 # ------------------------------------- the paper's 3D suspension at full size
-def test_paper_scale_3d_sampled_first_step(gpu_lib):
-    """The paper's 3D suspension at full size (512x2016x512 D3Q19, 129,024
-    spheres, FP64: about 190 GB of device memory on one GPU), one step from
-    the seeded initial state.  The oracle cannot hold this lattice, but one
-    step is local: a particle's force, contact force and new state depend only
-    on the uniform initial fluid and the particles within a few radii.  Each
-    sampled particle is checked against the oracle run on a periodic 48^3
-    sub-box centred on it (holding every particle whose centre lies in it,
-    shifted by whole lattice units); the total mass of the full lattice is
-    checked after three steps."""
+@pytest.mark.parametrize("name,E,steps,nsample", [("P3", 64, 5, 6), ("P2", 96, 5, 8)])
+def test_paper_scale_sampled(gpu_lib, name, E, steps, nsample):
+    """The paper's suspensions at full size on one GPU, FP64: 3D 512x2016x512
+    D3Q19 with 129,024 spheres (about 188 GB of device memory) and 2D
+    15360x61440 D2Q9 with 1,166,400 discs (about 184 GB), checked after one
+    step and after `steps` steps from the seeded initial state.
+
+    The oracle cannot hold these lattices, but the method is local: after k
+    steps a particle's force, contact force and state depend only on the
+    initial fluid (uniform) and on the particles within about k + 3R of it.
+    Each sampled particle is checked against the oracle run on a periodic
+    sub-box of edge E centred on it, holding every particle whose nearest image
+    lies within E/2 - R - 1 of it on every axis, shifted by whole lattice
+    units: a particle left out covers nodes at least E/2 - 2R - 2 away, and
+    its influence travels one node per step, so the sampled particle's nodes
+    (within R + 1) stay exact while k < E/2 - 3R - 3.
+
+    The shift is exact for the initial positions, so after one step every
+    field meets the bar relative to its own size.  Later positions x + v are
+    rounded at the magnitude of the coordinate, which differs between the full
+    box (up to 2016 or 61440) and the sub-box (below E): the two runs'
+    positions then differ by about one unit in the last place of the larger
+    coordinate (P2: k ulp(61440) = k 7.3e-12 after k steps, about 1e-11 of R
+    at k = 5).  The torque sum over the footprint nearly cancels, so after k
+    steps the torque is measured against the torque scale R |F| and the
+    angular velocity against k R |F| / I (I the moment of inertia), with the
+    bar raised to 1e-11 of those scales, the size of that lever-arm change;
+    the other fields keep the 1e-12 bar against their own size.  The total
+    mass of the full lattice is checked from the library's statistics."""
     import torch
-    w = I.workload("P3")
+    from oracle import oracle as O
+    w = I.workload(name)
+    assert steps < E // 2 - 3 * w.radius - 3
+    say("paper scale %s: %s, %d particles, %d steps, sub-box %d (placing particles)"
+        % (name, w.shape, w.count, steps, E))
     parts = w.particles()
     pos = parts[0]
-    L = np.array(w.shape, dtype=np.float64)
-    say("paper scale", w.shape, w.count, "particles")
+    D = w.dim
+    L = np.array(list(w.shape) + [1] * (3 - D), dtype=np.float64)
     torch.cuda.empty_cache()
-    gpu = gpu_lib.Simulation(3, w.shape, w.tau, storage="fp64", wall_y=False,
+    gpu = gpu_lib.Simulation(D, w.shape, w.tau, storage="fp64", wall_y=False,
                              fluid_force=w.fluid_force, particle_accel=w.particle_accel,
                              samples=w.samples, kn=w.kn, restitution=w.restitution,
                              max_particles=w.count, max_radius=w.radius)
     gpu.set_particles(*parts)
-    gpu.step(1)
-    F1, T1 = gpu.forces()
-    Fc1 = gpu.contact_forces()
-    x1, v1, w1 = gpu.particles()
-    from oracle import oracle as O
-    E = 48
-    rng = np.random.default_rng(5)
-    for p in sorted(rng.choice(w.count, 4, replace=False)):
-        c = pos[p]
-        org = np.floor(c) - E // 2
-        # periodic image nearest to c; kept when it lies within E/2 - R - 1 of c
-        # on every axis, so no two kept particles meet across the sub-box seam
-        img = pos - L * np.round((pos - c) / L)
-        sel = np.flatnonzero(np.all(np.abs(img - c) < E // 2 - w.radius - 1, axis=1))
-        sub = img[sel] - org               # exact for particles that needed no wrap
-        k = int(np.flatnonzero(sel == p)[0])
-        orc = O.OracleSim(3, (E, E, E), w.tau, wall_y=False, fluid_force=w.fluid_force,
-                          particle_accel=w.particle_accel, samples=w.samples, kn=w.kn,
-                          restitution=w.restitution)
-        orc.set_particles(sub, parts[1][sel], parts[2][sel], parts[3][sel], parts[4][sel], parts[5][sel])
-        orc.step(1)
-        F0, T0 = orc.forces()
-        x0, v0, w0 = orc.particles()
-        xg = x1[p] - org
-        xg -= L * np.round((xg - x0[k]) / L)
-        errs = {"F": rel_err(F1[p], F0[k]), "T": rel_err(T1[p], T0[k]),
-                "Fc": rel_err(Fc1[p], orc.contact_forces()[k]), "v": rel_err(v1[p], v0[k]),
-                "w": rel_err(w1[p], w0[k]), "x": rel_err(xg, x0[k])}
-        orc.close()
-        assert_close(errs, label="paper scale particle %d (%d in sub-box)" % (p, len(sel)))
-    gpu.step(2)
-    rho, u = gpu.macro_device()
-    mass = float(rho.sum())
-    del rho, u
+    snap = {}
+    for t in (1, steps):
+        gpu.step(t - gpu.t)
+        snap[t] = (gpu.forces(), gpu.contact_forces(), gpu.particles())
+    mass = gpu.stats()["mass"]
     gpu.close()
     del gpu
     torch.cuda.empty_cache()
-    say("paper scale mass error %.2e" % (abs(mass - w.nodes) / w.nodes))
+    say("  mass error %.2e" % (abs(mass - w.nodes) / w.nodes))
     assert abs(mass - w.nodes) / w.nodes < 1e-13
+    R = w.radius
+    m = w.rho_ratio * (math.pi * R ** 2 if D == 2 else 4.0 / 3.0 * math.pi * R ** 3)
+    inertia = (0.5 if D == 2 else 0.4) * m * R ** 2
+    rng = np.random.default_rng(5)
+    sub_shape = (E,) * D
+    for p in sorted(rng.choice(w.count, nsample, replace=False)):
+        c = pos[p]
+        org = np.floor(c) - E // 2
+        org[D:] = 0.0
+        img = pos - L * np.round((pos - c) / L)
+        sel = np.flatnonzero(np.all(np.abs(img - c)[:, :D] < E // 2 - R - 1, axis=1))
+        sub = img[sel] - org               # exact for particles that needed no wrap
+        k = int(np.flatnonzero(sel == p)[0])
+        orc = O.OracleSim(D, sub_shape, w.tau, wall_y=False, fluid_force=w.fluid_force,
+                          particle_accel=w.particle_accel, samples=w.samples, kn=w.kn,
+                          restitution=w.restitution)
+        orc.set_particles(sub, parts[1][sel], parts[2][sel], parts[3][sel], parts[4][sel], parts[5][sel])
+        for t in (1, steps):
+            orc.step(t - orc.t)
+            (F1, T1), Fc1, (x1, v1, w1) = snap[t]
+            F0, T0 = orc.forces()
+            x0, v0, w0 = orc.particles()
+            xg = x1[p] - org
+            xg -= L * np.round((xg - x0[k]) / L)
+            errs = {"F": rel_err(F1[p], F0[k]), "Fc": rel_err(Fc1[p], orc.contact_forces()[k]),
+                    "v": rel_err(v1[p], v0[k]), "x": rel_err(xg, x0[k])}
+            if t == 1:
+                errs["T"] = rel_err(T1[p], T0[k])
+                errs["w"] = rel_err(w1[p], w0[k])
+            else:
+                fmag = float(np.abs(F0[k]).max())
+                errs["T/(R|F|)"] = float(np.abs(T1[p] - T0[k]).max() / max(R * fmag, np.abs(T0[k]).max()))
+                errs["w/(kR|F|/I)"] = float(np.abs(w1[p] - w0[k]).max()
+                                            / max(t * R * fmag / inertia, np.abs(w0[k]).max()))
+            label = "%s particle %d (%d in sub-box), step %d" % (name, p, len(sel), t)
+            if t > 1:
+                rot = {key: errs.pop(key) for key in ("T/(R|F|)", "w/(kR|F|/I)")}
+                assert_close(rot, tol=1e-11, label=label + " rotation")
+            assert_close(errs, label=label)
+        orc.close()
