@@ -55,7 +55,10 @@
  * in the same order; in particular the footprint gives each thread a slab of
  * the outermost lattice axis and every thread walks the particles in
  * ascending id, so each node still accumulates its owners in ascending id.
- * orc_set_threads(1) gives the plain serial program.
+ * orc_set_threads(1) gives the plain serial program.  Loops over fewer
+ * nodes or particles than the parallel minimum (orc_set_parallel_minimum)
+ * stay on the calling thread, where a parallel region would cost more than
+ * the work.
  */
 #include <math.h>
 #ifdef _OPENMP
@@ -66,6 +69,10 @@
 #include <string.h>
 
 #define ORC_PI 3.141592653589793
+
+/* loops smaller than these run on the calling thread */
+static long par_min_nodes = 32768;
+static long par_min_particles = 256;
 
 /* ---------------------------------------------------------------- lattices */
 /* D2Q9: 0 rest; 1..4 axis; 5..8 diagonals. */
@@ -370,7 +377,7 @@ orc_sim *orc_create(int dim, int nx, int ny, int nz, int wall_y, double tau,
     double u0[3] = {0.0, 0.0, 0.0};
     for (int i = 0; i < s->L.Q; i++) {
         double fe = feq_i(&s->L, i, 1.0, u0);
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) if (s->N >= par_min_nodes)
         for (long n = 0; n < s->N; n++) s->f[(long)i * s->N + n] = fe;
     }
     return s;
@@ -467,7 +474,7 @@ int orc_get_f(const orc_sim *s, double *f) {
 /* Moments of the pre-collision f(x,t): rho[N], u[D][N] = sum_i f_i c_i / rho. */
 int orc_get_macro(const orc_sim *s, double *rho, double *u) {
     const orc_lattice *L = &s->L;
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) if (s->N >= par_min_nodes)
     for (long n = 0; n < s->N; n++) {
         double r = 0.0, j[3] = {0.0, 0.0, 0.0};
         for (int i = 0; i < L->Q; i++) {
@@ -555,7 +562,7 @@ static void footprint_slab(orc_sim *s, int o0, int o1) {
 
 static void footprint(orc_sim *s) {
     const long N = s->N;
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) if (N >= par_min_nodes)
     for (long n = 0; n < N; n++) {
         s->ctot[n] = 0;
         s->vnum[n] = 0.0;
@@ -565,7 +572,7 @@ static void footprint(orc_sim *s) {
     /* slabs of the outermost axis are disjoint node sets */
     const int nouter = s->L.D == 3 ? s->nz : s->ny;
     const int nslab = nouter < 64 ? nouter : 64;
-#pragma omp parallel for schedule(dynamic, 1)
+#pragma omp parallel for schedule(dynamic, 1) if (N >= par_min_nodes)
     for (int k = 0; k < nslab; k++)
         footprint_slab(s, (int)((long)nouter * k / nslab), (int)((long)nouter * (k + 1) / nslab));
 }
@@ -632,7 +639,7 @@ static void collide_all(orc_sim *s) {
     const orc_lattice *L = &s->L;
     const int Q = L->Q;
     const int Smax = L->D == 2 ? s->S * s->S : s->S * s->S * s->S;
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) if (s->N >= par_min_nodes)
     for (long n = 0; n < s->N; n++) {
         double fin[19], fout[19], vs[3] = {0.0, 0.0, 0.0}, q[3];
         for (int i = 0; i < Q; i++) fin[i] = s->f[(long)i * s->N + n];
@@ -652,7 +659,7 @@ static void collide_all(orc_sim *s) {
 static void stream_all(orc_sim *s) {
     const orc_lattice *L = &s->L;
     /* every (direction, target node) is written by exactly one source */
-#pragma omp parallel for collapse(2) schedule(static)
+#pragma omp parallel for collapse(2) schedule(static) if (s->N >= par_min_nodes)
     for (int z = 0; z < s->nz; z++)
         for (int y = 0; y < s->ny; y++)
             for (int x = 0; x < s->nx; x++) {
@@ -673,7 +680,7 @@ static void stream_all(orc_sim *s) {
 /* Eq. (3) with shares: F_p = -sum_n s_pn q_n, T_p = -sum_n r_pn x (s_pn q_n). */
 static void hydro_forces(orc_sim *s) {
     const int D = s->L.D;
-#pragma omp parallel for schedule(dynamic, 16)
+#pragma omp parallel for schedule(dynamic, 16) if (s->np >= par_min_particles)
     for (int p = 0; p < s->np; p++) {
         orc_acc F[3] = {{0, 0}, {0, 0}, {0, 0}}, T[3] = {{0, 0}, {0, 0}, {0, 0}};
         int lo[3], hi[3];
@@ -717,7 +724,7 @@ static void hydro_forces(orc_sim *s) {
 static void dem_forces_impl(int D, int np, const double *x, const double *v,
                             const double *R, const double *m, double kn, double ce,
                             const double Lbox[3], int wall_y, double *Fc) {
-#pragma omp parallel for schedule(dynamic, 16)
+#pragma omp parallel for schedule(dynamic, 16) if (np >= par_min_particles)
     for (int i = 0; i < np; i++) {
         double F[3] = {0.0, 0.0, 0.0};
         for (int j = 0; j < np; j++) {
@@ -785,7 +792,7 @@ static double wrap_pos(double x, double Lp) {
 static void integrate(orc_sim *s) {
     const int D = s->L.D;
     double Lb[3] = {(double)s->nx, (double)s->ny, (double)s->nz};
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) if (s->np >= par_min_particles)
     for (int p = 0; p < s->np; p++) {
         if (s->fixed[p]) continue;
         for (int a = 0; a < D; a++) {
@@ -881,6 +888,13 @@ double orc_beta(double eps, double tau) { return beta_of_eps(eps, tau); }
 /* Number of threads the oracle's parallel loops use from now on (n >= 1;
  * n <= 0 selects every core).  Returns the number in effect; 1 when built
  * without OpenMP. */
+/* Smallest node loop and particle loop that run on several threads (values
+ * below 1 are taken as 1).  Results do not depend on them. */
+void orc_set_parallel_minimum(long nodes, long particles) {
+    par_min_nodes = nodes < 1 ? 1 : nodes;
+    par_min_particles = particles < 1 ? 1 : particles;
+}
+
 int orc_set_threads(int n) {
 #ifdef _OPENMP
     if (n <= 0) n = omp_get_num_procs();

@@ -57,6 +57,8 @@ def lib():
         L.orc_eps_table_count.restype = C.c_int
         L.orc_set_threads.argtypes = [C.c_int]
         L.orc_set_threads.restype = C.c_int
+        L.orc_set_parallel_minimum.argtypes = [C.c_long, C.c_long]
+        L.orc_set_parallel_minimum.restype = None
         _lib = L
     return _lib
 
@@ -65,6 +67,12 @@ def set_threads(n):
     """Threads of the oracle's parallel loops from now on (n <= 0: every
     core); returns the number in effect.  Results do not depend on it."""
     return lib().orc_set_threads(int(n))
+
+
+def set_parallel_minimum(nodes=32768, particles=256):
+    """Smallest node loop and particle loop that run on several threads (the
+    defaults keep small lattices on one thread).  Results do not depend on it."""
+    lib().orc_set_parallel_minimum(int(nodes), int(particles))
 
 
 def _dp(a):

@@ -16,6 +16,7 @@ from paper_1011_2613_amd import inputs as I
 
 def _run(dim, box, n, R, threads, steps, wall_y, seed):
     O.set_threads(threads)
+    O.set_parallel_minimum(1, 1)  # these small boxes take the threaded path too
     try:
         pos = I.place_particles(dim, box, R, n, seed, wall_y=wall_y)
         # one overlapping pair (a contact from the first step) and, with
@@ -47,6 +48,7 @@ def _run(dim, box, n, R, threads, steps, wall_y, seed):
         return out
     finally:
         O.set_threads(0)
+        O.set_parallel_minimum()
 
 
 @pytest.mark.parametrize("dim,box,n,R,wall_y", [
