@@ -136,6 +136,60 @@ def run_variant(binding, inputs, w, parts, storage, steps, warmup, eps="sampling
     }
 
 
+def precision_report(binding, w, parts, steps=500, window=100):
+    """FP32-shifted and FP16 storage against the FP64 GPU run of the same
+    workload from the same state, `steps` steps: the per-particle drag error
+    |F_low - F_64| / |F_64| averaged over particles and the last `window`
+    steps (and its largest value), the error of the suspension-mean drag
+    (lbm_get_stats) over the same window, the velocity error
+    max |u_low - u_64| / max |u_64| over all nodes at the end, and for FP16 the
+    fraction of stored values g_i / w_i that are binary16 subnormals (nonzero
+    and below 2^-14 in magnitude)."""
+    import numpy as np
+    import torch
+    Q = 9 if w.dim == 2 else 19
+    wts = np.array([4 / 9] + [1 / 9] * 4 + [1 / 36] * 4) if w.dim == 2 else \
+        np.array([1 / 3] + [1 / 18] * 6 + [1 / 36] * 12)
+    ref = {}
+    out = {}
+    for storage in ("fp64", "fp32s", "fp16s"):
+        sim = binding.Simulation(w.dim, w.shape, w.tau, storage=storage, wall_y=w.wall_y,
+                                 fluid_force=w.fluid_force, particle_accel=w.particle_accel,
+                                 samples=w.samples, kn=w.kn, restitution=w.restitution,
+                                 max_particles=w.count, max_radius=w.radius)
+        sim.set_particles(*parts)
+        sim.step(steps - window)
+        F, md = [], []
+        for _ in range(window):
+            sim.step(1)
+            F.append(sim.forces()[0])
+            md.append(sim.stats()["mean_drag"])
+        F, md = np.array(F), np.array(md)
+        _, u = sim.macro_device()
+        if storage == "fp64":
+            ref = {"F": F, "md": md, "u": u}
+        else:
+            e = np.linalg.norm(F - ref["F"], axis=2) / np.linalg.norm(ref["F"], axis=2)
+            emd = np.linalg.norm(md - ref["md"], axis=1) / np.linalg.norm(ref["md"], axis=1)
+            uerr = float((u - ref["u"]).abs().max() / ref["u"].abs().max())
+            rec = {"steps": steps, "window": window, "drag_rel_err_mean": float(e.mean()),
+                   "drag_rel_err_max": float(e.max()), "mean_drag_rel_err": float(emd.mean()),
+                   "velocity_rel_err_inf": uerr}
+            if storage == "fp16s":
+                f = sim.get_f_device().reshape(Q, -1)
+                wt = torch.as_tensor(wts, device=f.device).reshape(Q, 1)
+                h = (f - wt) / wt
+                sub = ((h != 0) & (h.abs() < 2.0 ** -14)).sum().item()
+                rec["fp16_subnormal_fraction"] = sub / h.numel()
+                del f, h
+            out[storage] = rec
+        del u
+        sim.close()
+        del sim
+        torch.cuda.empty_cache()
+    return out
+
+
 def ensemble_bench(binding, nbox=512, steps=200, check_every=100):
     """Batched drag ensemble at the drag-data size: 512 boxes (edges 32-96,
     1-64 spheres of radius 4-8), autotuned tile shape and launch mode, FP32
@@ -277,6 +331,8 @@ def main():
                          '64/128/192/256 with an optional "/xcd" workgroup order and "/cuN" cap of '
                          'N workgroups per CU, or per variant, e.g. "fp64=256/xcd/cu3,fp32s=64"')
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-precision", action="store_true",
+                    help="skip the FP32s / FP16 error measurement against the FP64 run")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the batched-ensemble and closure measurements")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -340,6 +396,12 @@ def main():
                      for v, r in res.items() if v != "fp64"},
         "device": torch.cuda.get_device_name(0),
     }
+    if not args.no_precision:
+        prec = precision_report(binding, w, parts)
+        for v, rec in prec.items():
+            if v in out["variants"]:
+                out["variants"][v]["errors_vs_fp64"] = rec
+        print("# precision: %s" % prec, file=sys.stderr, flush=True)
     if not args.no_extras:
         out["ensemble"] = ensemble_bench(binding)
         print("# ensemble: %s" % out["ensemble"], file=sys.stderr, flush=True)

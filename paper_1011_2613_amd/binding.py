@@ -231,6 +231,15 @@ class Simulation:
         self._check(load().lbm_get_distributions(self._ctx, _ptr(f), LBM_HOST))
         return f
 
+    def get_f_device(self):
+        """Pre-collision populations [Q][...] binary64 as a device tensor,
+        converted from the storage format on the library's stream."""
+        torch = self._torch
+        f = torch.empty((self.Q,) + self.field_shape, dtype=torch.float64, device=self.device)
+        self._check(load().lbm_get_distributions(self._ctx, _ptr(f), LBM_DEVICE))
+        torch.cuda.current_stream(self.device).wait_stream(self.stream)
+        return f
+
     def step(self, n=1):
         self._check(load().lbm_step(self._ctx, int(n)))
 

@@ -3,8 +3,15 @@
 FP32-shifted storage (g_i = f_i - w_i in binary32, binary32 arithmetic) must
 keep the mean relative drag error, averaged over particles and over the last
 100 steps, within 1e-3 of FP64.  FP16 storage (g_i / w_i in binary16) has no
-target; its errors are reported.  Particle-side arithmetic is binary64 in all
-modes.
+target in the workloads; its bar is a regression bar derived from the format:
+every stored deviation is rounded to a relative 2^-11 (U16, the binary16 unit
+roundoff) once per step, and the drag, a sum over the footprint of such
+deviations, settles within a few response times, so its error stays within a
+small multiple of U16; 10 U16 = 4.9e-3 is the bar (measured: C1 3.5e-3,
+sedimenting D3Q19 box 1.9e-4).  Storing the populations themselves instead of
+their scaled deviations would lose them entirely (ulp(1/3) in binary16 is
+2.4e-4 against deviations of 1e-5) and give errors of order one.
+Particle-side arithmetic is binary64 in all modes.
 """
 import numpy as np
 import pytest
@@ -36,7 +43,11 @@ def drag_errors(orc, gpu, steps, window):
     return float(errs.mean()), float(errs.max()), rel_err(u1, u0)
 
 
-@pytest.mark.parametrize("storage,bound", [("fp32s", 1e-3), ("fp16s", 0.5)])
+U16 = 2.0 ** -11
+FP16_BAR = 10 * U16
+
+
+@pytest.mark.parametrize("storage,bound", [("fp32s", 1e-3), ("fp16s", FP16_BAR)])
 def test_c1_drag_error(gpu_lib, storage, bound):
     w = I.workload("C1")
     parts = w.particles()
@@ -48,7 +59,7 @@ def test_c1_drag_error(gpu_lib, storage, bound):
     assert mean <= bound
 
 
-@pytest.mark.parametrize("storage,bound", [("fp32s", 1e-3), ("fp16s", 0.5)])
+@pytest.mark.parametrize("storage,bound", [("fp32s", 1e-3), ("fp16s", FP16_BAR)])
 def test_d3q19_sedimenting_drag_error(gpu_lib, storage, bound):
     box = (40, 48, 32)
     n = 10
@@ -73,3 +84,40 @@ def test_shifted_rest_state_is_exact(gpu_lib):
     _, u = sim.macro()
     F, _ = sim.forces()
     assert np.all(u == 0.0) and np.all(F == 0.0)
+
+
+def test_c3_storage_errors_against_gpu_fp64(gpu_lib):
+    """The 3D suspension at full size (192x756x192, 8317 spheres): FP32-shifted
+    and FP16 storage against the FP64 run on the GPU (bitwise the oracle's, see
+    the parity tests) from the same state, 500 steps; per-particle drag error
+    averaged over particles and the last 100 steps, and the velocity error
+    max |du| / max |u| at the end."""
+    import torch
+    w = I.workload("C3")
+    parts = w.particles()
+    steps, window = 500, 100
+    ref = None
+    res = {}
+    for storage in ("fp64", "fp32s", "fp16s"):
+        say("C3", storage, steps, "steps")
+        sim = gpu_lib.simulation_for(w, storage)
+        sim.step(steps - window)
+        F = []
+        for _ in range(window):
+            sim.step(1)
+            F.append(sim.forces()[0])
+        F = np.array(F)
+        _, u = sim.macro_device()
+        if ref is None:
+            ref = (F, u)
+        else:
+            e = np.linalg.norm(F - ref[0], axis=2) / np.linalg.norm(ref[0], axis=2)
+            uerr = float((u - ref[1]).abs().max() / ref[1].abs().max())
+            res[storage] = (float(e.mean()), float(e.max()), uerr)
+            say("C3 %s: mean drag err %.3e, max %.3e, velocity err %.3e" % ((storage,) + res[storage]))
+        del u
+        sim.close()
+        del sim
+        torch.cuda.empty_cache()
+    assert res["fp32s"][0] <= 1e-3
+    assert res["fp16s"][0] <= FP16_BAR
