@@ -205,6 +205,27 @@ enum { LBM_ORDER_LINEAR = 0, LBM_ORDER_XCD = 1 };
 int lbm_set_lattice_block(lbm_ctx *ctx, int threads, int order, int cu_groups);
 int lbm_get_lattice_block(const lbm_ctx *ctx, int *threads, int *order, int *cu_groups);
 
+/* DEM neighbour search ("Parallel implementation": a neighbour list rebuilt
+ * about every 100th step, after Xu et al.).  every = 0 (a new context's
+ * default): the cell list is rebuilt every step and the contacts gathered from
+ * it.  every >= 1: each particle keeps the list of the particles within
+ * R_i + R_j + skin of it (minimum image) at the last build; the list is rebuilt
+ * on the device when `every` steps have passed since the build, or earlier
+ * when some particle has moved 0.49 skin or more since the build (the
+ * displacement guard: a pair missing from the lists cannot touch before
+ * that), and at the first step after lbm_set_particles, lbm_load or this call.
+ * Contacts then sum the touching listed neighbours in ascending id, as the
+ * per-step search does: both modes give the same bits.  The cell edge becomes
+ * 2 R_max + skin.  A list holds at most 2 LBM_MAX_CONTACTS entries
+ * (LBM_E_CONTACT_OVERFLOW beyond).  Takes effect from the next step.  Errors:
+ * LBM_E_INVALID (every < 0; skin outside (0, 2 max_radius] when every >= 1;
+ * the cell grid would exceed the reserved budget). */
+int lbm_set_neighbour_list(lbm_ctx *ctx, int every, double skin);
+
+/* The neighbour-search mode in force and, in builds (may be NULL), the number
+ * of list builds so far (synchronises). */
+int lbm_get_neighbour_list(lbm_ctx *ctx, int *every, double *skin, int64_t *builds);
+
 /* Chooses the lattice kernel's launch shape by measurement.  Each of the 24
  * candidates (width 64, 128, 192, 256 for k % 4 = 0..3, order (k / 4) % 2,
  * cap 0, 4, 3 workgroups per CU for k / 8 = 0..2; XCD candidates skipped

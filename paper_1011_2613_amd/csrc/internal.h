@@ -45,6 +45,7 @@ enum : uint32_t {
 constexpr int MAX_OWNERS = 4;
 constexpr int MAX_CONTACTS = 32;
 constexpr int CELL_CAP = 16;
+constexpr int NL_CAP = 2 * MAX_CONTACTS;  // neighbour-list entries per particle
 constexpr int SLOT_COUNT_BITS = 10;  // count of sub-samples (<= 512) in the low bits
 
 // eps lookup table (Eq. 6): bins of rho = |r| - R and of the folded direction
@@ -157,6 +158,16 @@ struct CellArgs {
     int D;
     double kn, ce;
     double ap[3];
+    // neighbour-list mode: lists of the pairs within R_i + R_j + skin, rebuilt
+    // after `every` steps or when a particle has moved skin / 2 since the build
+    int every;
+    double skin;
+    int *nl;               // [P][NL_CAP] neighbour ids, ascending
+    int *nl_len;           // [P]
+    double *xb;            // [3][P] positions at the last build
+    int *nl_state;         // [0] rebuild flag, [1] steps since the last build
+    int64_t *nl_builds;    // builds so far
+    int64_t ncell;         // ncx * ncy * ncz
 };
 
 // Suspension-wide sums (lbm_get_stats): node pass over the lattice rows with a
@@ -274,5 +285,10 @@ hipError_t launch_force(const ForceArgs &a, hipStream_t s);
 hipError_t launch_list_q(const ForceArgs &a, double *out, hipStream_t s);
 hipError_t launch_cells(const CellArgs &a, hipStream_t s);
 hipError_t launch_dem(const CellArgs &a, hipStream_t s);
+// neighbour-list mode: the guard, a conditional rebuild (cells and lists) and
+// the contacts from the lists; phase_mid is called between the rebuild and the
+// contacts (for the per-phase timing)
+hipError_t launch_nl_rebuild(const CellArgs &a, hipStream_t s);
+hipError_t launch_nl_contacts(const CellArgs &a, hipStream_t s);
 
 }  // namespace lbimb

@@ -6,6 +6,8 @@
 // order differs from a sequential loop (the per-particle force reduction) use
 // error-free TwoSum accumulation (Ogita, Rump & Oishi 2005) so the rounded
 // result does not depend on the reduction tree.
+#include <algorithm>
+
 #include "internal.h"
 
 namespace lbimb {
@@ -652,6 +654,26 @@ __device__ __forceinline__ bool pair_force(const CellArgs &a, int i, int j, doub
     return true;
 }
 
+// Wall contacts of particle i (Eqs. 4-5 against a wall at rest, m_eff = m_i),
+// added to F after the pair forces.
+__device__ __forceinline__ void wall_force(const CellArgs &a, int i, double F[3]) {
+    if (!a.g.wall_y) return;
+    const int P = a.P.np;
+    const double eta = a.ce * sqrt(a.P.m[i] * a.kn);
+    const double y = a.P.x[P + i];
+    const double vy = a.P.v[P + i];
+    const double dl = a.P.R[i] - (y + 0.5);
+    if (dl > 0.0) {
+        const double fmag = a.kn * dl - eta * vy;
+        F[1] = F[1] + fmag;
+    }
+    const double du = a.P.R[i] - ((a.g.Ly - 0.5) - y);
+    if (du > 0.0) {
+        const double fmag = a.kn * du - eta * (-vy);
+        F[1] = F[1] - fmag;
+    }
+}
+
 // One wavefront per particle: each lane scans one neighbour cell, touching
 // neighbours are gathered in LDS, sorted by id, and the pair forces are added
 // in ascending id (then the walls) by the first lane.
@@ -704,22 +726,153 @@ __global__ __launch_bounds__(256) void k_dem(CellArgs a) {
         }
         double F[3] = {0.0, 0.0, 0.0};
         for (int s = 0; s < nl; s++) pair_force(a, i, l[s], F);
-        if (a.g.wall_y) {
-            const double eta = a.ce * sqrt(a.P.m[i] * a.kn);
-            const double y = a.P.x[P + i];
-            const double vy = a.P.v[P + i];
-            const double dl = a.P.R[i] - (y + 0.5);
-            if (dl > 0.0) {
-                const double fmag = a.kn * dl - eta * vy;
-                F[1] = F[1] + fmag;
-            }
-            const double du = a.P.R[i] - ((a.g.Ly - 0.5) - y);
-            if (du > 0.0) {
-                const double fmag = a.kn * du - eta * (-vy);
-                F[1] = F[1] - fmag;
+        wall_force(a, i, F);
+        for (int d = 0; d < 3; d++) a.P.Fc[d * P + i] = F[d];
+    }
+}
+
+// ------------------------------------------------------ neighbour-list mode
+// The lists hold, in ascending id, every j with |r_i - r_j| < R_i + R_j + skin
+// (minimum image) at the last build.  A pair missing from the lists was at
+// least that far apart, so it can only touch after one of the two moved at
+// least skin / 2; the guard rebuilds before any particle has moved 0.49 skin
+// since the build, and after `every` steps in any case.  Contacts then sum the
+// touching listed neighbours in ascending id, the order of k_dem, so both
+// modes give the same bits.
+
+// Guard: raises the rebuild flag when a particle moved 0.49 skin or more since
+// the last build, or the lists are `every` steps old.
+__global__ void k_nl_check(CellArgs a) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    const int P = a.P.np;
+    if (p == 0 && a.nl_state[1] >= a.every) atomicOr(&a.nl_state[0], 1);
+    if (p >= P) return;
+    double d2 = 0.0;
+    for (int ax = 0; ax < a.D; ax++) {
+        double dd = a.P.x[ax * P + p] - a.xb[ax * P + p];
+        if (!(ax == 1 && a.g.wall_y)) dd = pdisp(dd, ax == 0 ? a.g.Lx : (ax == 1 ? a.g.Ly : a.g.Lz));
+        d2 = d2 + dd * dd;
+    }
+    const double lim = 0.49 * a.skin;
+    if (!(d2 < lim * lim)) atomicOr(&a.nl_state[0], 1);
+}
+
+// Cell binning, on rebuild steps only (the counts are zero on entry).
+__global__ void k_nl_cells(CellArgs a) {
+    if (!a.nl_state[0]) return;
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    const int P = a.P.np;
+    if (p >= P) return;
+    const int cx = cell_coord(a, 0, a.P.x[p]);
+    const int cy = cell_coord(a, 1, a.P.x[P + p]);
+    const int cz = a.D == 3 ? cell_coord(a, 2, a.P.x[2 * P + p]) : 0;
+    const int c = cx + a.ncx * (cy + a.ncy * cz);
+    const int slot = atomicAdd(&a.cell_count[c], 1);
+    if (slot < CELL_CAP) a.cell_ids[c * CELL_CAP + slot] = p;
+    else atomicOr(a.flags, FLAG_CELL_OVERFLOW);
+}
+
+// True when j lies within R_i + R_j + skin of i (minimum image).
+__device__ __forceinline__ bool nl_candidate(const CellArgs &a, int i, int j) {
+    const int P = a.P.np;
+    double d2 = 0.0;
+    for (int ax = 0; ax < a.D; ax++) {
+        double dd = a.P.x[ax * P + i] - a.P.x[ax * P + j];
+        if (!(ax == 1 && a.g.wall_y)) dd = pdisp(dd, ax == 0 ? a.g.Lx : (ax == 1 ? a.g.Ly : a.g.Lz));
+        d2 = d2 + dd * dd;
+    }
+    const double lim = (a.P.R[i] + a.P.R[j]) + a.skin;
+    return d2 < lim * lim;
+}
+
+// List build, on rebuild steps only: one wavefront per particle, each lane
+// scans one neighbour cell (cell edge >= 2 R_max + skin), the candidates are
+// gathered in LDS and sorted by id; the build positions are recorded.
+__global__ __launch_bounds__(256) void k_nl_build(CellArgs a) {
+    if (!a.nl_state[0]) return;
+    __shared__ int list[4][NL_CAP];
+    __shared__ int nlist[4];
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int i = blockIdx.x * 4 + wave;
+    const int P = a.P.np;
+    const int D = a.D;
+    if (lane == 0) nlist[wave] = 0;
+    __syncthreads();
+    if (i < P) {
+        const int c0 = cell_coord(a, 0, a.P.x[i]);
+        const int c1 = cell_coord(a, 1, a.P.x[P + i]);
+        const int c2 = D == 3 ? cell_coord(a, 2, a.P.x[2 * P + i]) : 0;
+        int ox[3], oy[3], oz[3];
+        const int nxc = axis_cells(c0, a.ncx, true, ox);
+        const int nyc = axis_cells(c1, a.ncy, !a.g.wall_y, oy);
+        int nzc = 1;
+        oz[0] = 0;
+        if (D == 3) nzc = axis_cells(c2, a.ncz, true, oz);
+        if (lane < nxc * nyc * nzc) {
+            const int kx = lane % nxc, ky = (lane / nxc) % nyc, kz = lane / (nxc * nyc);
+            const int c = ox[kx] + a.ncx * (oy[ky] + a.ncy * oz[kz]);
+            const int cnt = min(a.cell_count[c], CELL_CAP);
+            for (int s = 0; s < cnt; s++) {
+                const int j = a.cell_ids[c * CELL_CAP + s];
+                if (j == i || !nl_candidate(a, i, j)) continue;
+                const int slot = atomicAdd(&nlist[wave], 1);
+                if (slot < NL_CAP) list[wave][slot] = j;
+                else atomicOr(a.flags, FLAG_CONTACT_OVERFLOW);
             }
         }
-        for (int d = 0; d < 3; d++) a.P.Fc[d * P + i] = F[d];
+        if (lane < D) a.xb[lane * P + i] = a.P.x[lane * P + i];
+    }
+    __syncthreads();
+    if (i < P && lane == 0) {
+        int *l = list[wave];
+        const int nl = min(nlist[wave], NL_CAP);
+        for (int s = 1; s < nl; s++) {
+            const int v = l[s];
+            int t = s - 1;
+            while (t >= 0 && l[t] > v) {
+                l[t + 1] = l[t];
+                t--;
+            }
+            l[t + 1] = v;
+        }
+        for (int s = 0; s < nl; s++) a.nl[(int64_t)i * NL_CAP + s] = l[s];
+        a.nl_len[i] = nl;
+    }
+}
+
+// Contacts from the lists (Eqs. 4-5): one thread per particle, the touching
+// listed neighbours in ascending id, then the walls.
+__global__ void k_dem_list(CellArgs a) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int P = a.P.np;
+    if (i >= P) return;
+    const int n = a.nl_len[i];
+    int touching = 0;
+    double F[3] = {0.0, 0.0, 0.0};
+    for (int s = 0; s < n; s++) touching += pair_force(a, i, a.nl[(int64_t)i * NL_CAP + s], F) ? 1 : 0;
+    if (touching > MAX_CONTACTS) atomicOr(a.flags, FLAG_CONTACT_OVERFLOW);
+    wall_force(a, i, F);
+    for (int d = 0; d < 3; d++) a.P.Fc[d * P + i] = F[d];
+}
+
+// After a rebuild: clear the cell counts for the next one.
+__global__ void k_nl_clear(CellArgs a) {
+    if (!a.nl_state[0]) return;
+    for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < a.ncell;
+         c += (int64_t)gridDim.x * blockDim.x)
+        a.cell_count[c] = 0;
+}
+
+// Ages the lists and lowers the rebuild flag (one thread, after every other
+// kernel of the step's neighbour work has read the flag).
+__global__ void k_nl_finish(CellArgs a) {
+    if (a.nl_state[0]) {
+        a.nl_state[0] = 0;
+        a.nl_state[1] = 1;
+        *a.nl_builds = *a.nl_builds + 1;
+    } else {
+        a.nl_state[1] = a.nl_state[1] + 1;
     }
 }
 
@@ -784,6 +937,23 @@ hipError_t launch_cells(const CellArgs &a, hipStream_t s) {
 hipError_t launch_dem(const CellArgs &a, hipStream_t s) {
     if (a.P.np == 0) return hipSuccess;
     hipLaunchKernelGGL(k_dem, dim3(blocks_for(a.P.np, 4)), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_nl_rebuild(const CellArgs &a, hipStream_t s) {
+    if (a.P.np == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_nl_check, dim3(blocks_for(a.P.np, 256)), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(k_nl_cells, dim3(blocks_for(a.P.np, 256)), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(k_nl_build, dim3(blocks_for(a.P.np, 4)), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_nl_contacts(const CellArgs &a, hipStream_t s) {
+    if (a.P.np == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_dem_list, dim3(blocks_for(a.P.np, 256)), dim3(256), 0, s, a);
+    const unsigned cb = (unsigned)std::min<int64_t>((a.ncell + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_nl_clear, dim3(cb), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(k_nl_finish, dim3(1), dim3(1), 0, s, a);
     return hipGetLastError();
 }
 

@@ -39,7 +39,7 @@ struct Layout {
     size_t off_list, off_list_len;
     int list_cap;
     double rmax;
-    size_t off_cc, off_cid, off_flags, off_tab, off_stats, total;
+    size_t off_cc, off_cid, off_flags, off_tab, off_stats, off_nl, off_nl_len, off_xb, off_nl_state, total;
 };
 
 int validate(const lbm_config *c, std::string &msg) {
@@ -108,6 +108,11 @@ Layout make_layout(const lbm_config *c) {
     L.off_tab = take((size_t)EPS_TAB_NRHO * EPS_TAB_NT * EPS_TAB_NT * 2);
     // lbm_get_stats: node-pass partials, one row per particle, the totals
     L.off_stats = take(((size_t)STATS_NODE_GROUPS * 4 + P * STATS_PK + 4 + STATS_PK) * 8);
+    // neighbour-list mode: lists, build positions, guard state and build count
+    L.off_nl = take(P * NL_CAP * 4);
+    L.off_nl_len = take(P * 4);
+    L.off_xb = take(3 * P * 8);
+    L.off_nl_state = take(64);
     L.total = o;
     return L;
 }
@@ -144,6 +149,9 @@ struct lbm_ctx {
     int lb_width;  // lattice kernel workgroup width, 0 for the built-in rule
     int lb_order;  // lattice kernel workgroup order, LBM_ORDER_LINEAR / _XCD
     int lb_cu_groups;  // lattice kernel workgroups per CU at most, 0: no cap
+    int nl_every;      // 0: cell list every step; else neighbour lists, rebuilt after nl_every steps at most
+    double nl_skin;    // list margin beyond contact
+    double prmax;      // largest radius of the current particles
     bool rec_open;
     std::vector<TimedEvent> events;
     size_t ev_used;
@@ -198,13 +206,15 @@ void *state(lbm_ctx *c, int which) { return c->ws + (which == 0 ? c->L.off_fA : 
 
 uint32_t *flags(lbm_ctx *c) { return wsp<uint32_t>(c, c->L.off_flags); }
 
-// DEM cell grid for np particles of largest radius rmax: cell edge >= 2 rmax,
-// the count bounded by the reserved budget.
+// DEM cell grid for np particles of largest radius rmax: cell edge >= 2 rmax
+// (plus the skin in neighbour-list mode, where the lists reach that far), the
+// count bounded by the reserved budget.
 void cell_grid(const lbm_ctx *c, int np, double rmax, int nc[3]) {
     const double Lb[3] = {c->g.Lx, c->g.Ly, c->g.Lz};
     nc[0] = nc[1] = nc[2] = 1;
     if (np < 1) return;
-    for (int a = 0; a < c->L.D; a++) nc[a] = std::max(1, (int)std::floor(Lb[a] / (2.0 * rmax)));
+    const double edge = 2.0 * rmax + (c->nl_every > 0 ? c->nl_skin : 0.0);
+    for (int a = 0; a < c->L.D; a++) nc[a] = std::max(1, (int)std::floor(Lb[a] / edge));
     while ((int64_t)nc[0] * nc[1] * nc[2] > c->L.cell_budget)
         for (int a = 0; a < c->L.D; a++) nc[a] = std::max(1, nc[a] / 2);
 }
@@ -241,7 +251,25 @@ CellArgs cell_args(lbm_ctx *c) {
     a.kn = c->cfg.kn;
     a.ce = c->ce;
     for (int d = 0; d < 3; d++) a.ap[d] = c->cfg.particle_accel[d];
+    a.every = c->nl_every;
+    a.skin = c->nl_skin;
+    a.nl = wsp<int>(c, c->L.off_nl);
+    a.nl_len = wsp<int>(c, c->L.off_nl_len);
+    a.xb = wsp<double>(c, c->L.off_xb);
+    a.nl_state = wsp<int>(c, c->L.off_nl_state);
+    a.nl_builds = wsp<int64_t>(c, c->L.off_nl_state + 8);
+    a.ncell = (int64_t)c->ncx * c->ncy * c->ncz;
     return a;
+}
+
+// Neighbour-list mode: the next step rebuilds (new particles, a new cell grid
+// or a mode change); the cell counts start at zero.
+hipError_t nl_reset(lbm_ctx *c) {
+    hipError_t e = launch_fill_u32(wsp<uint32_t>(c, c->L.off_nl_state), 0u, 4, c->stream);
+    if (e == hipSuccess) e = launch_fill_u32(wsp<uint32_t>(c, c->L.off_nl_state), 1u, 1, c->stream);
+    if (e == hipSuccess)
+        e = launch_fill_u32(wsp<uint32_t>(c, c->L.off_cc), 0u, (int64_t)c->ncx * c->ncy * c->ncz, c->stream);
+    return e;
 }
 
 FootArgs foot_args(lbm_ctx *c) {
@@ -373,10 +401,10 @@ hipError_t enqueue_step(lbm_ctx *c, int from, hipStream_t s, int slot) {
         if ((e = hipEventRecord(c->ev_fork[slot], s)) != hipSuccess) return e;
         if ((e = hipStreamWaitEvent(d, c->ev_fork[slot], 0)) != hipSuccess) return e;
         phase_begin(c, 3, d);
-        if ((e = launch_cells(ca, d)) != hipSuccess) return e;
+        if ((e = c->nl_every > 0 ? launch_nl_rebuild(ca, d) : launch_cells(ca, d)) != hipSuccess) return e;
         phase_end(c, d);
         phase_begin(c, 4, d);
-        if ((e = launch_dem(ca, d)) != hipSuccess) return e;
+        if ((e = c->nl_every > 0 ? launch_nl_contacts(ca, d) : launch_dem(ca, d)) != hipSuccess) return e;
         phase_end(c, d);
         if ((e = hipEventRecord(c->ev_join[slot], d)) != hipSuccess) return e;
         FootArgs fa = foot_args(c);
@@ -539,6 +567,9 @@ int lbm_create(const lbm_config *cfg, void *workspace, size_t ws_bytes, void *hi
     c->lb_width = 0;
     c->lb_order = LBM_ORDER_LINEAR;
     c->lb_cu_groups = 0;
+    c->nl_every = 0;
+    c->nl_skin = 1.0;
+    c->prmax = 0.0;
     c->rec_open = false;
     c->ev_used = 0;
     for (int k = 0; k < LBM_NPHASES; k++) { c->phase_ms[k] = 0.0; c->phase_n[k] = 0; }
@@ -739,6 +770,8 @@ int lbm_set_particles(lbm_ctx *c, int64_t n, const double *pos, const double *ve
     HIPCHK(c, hipMemcpy(wsp<double>(c, c->L.off_I), I.data(), np * 8, hipMemcpyHostToDevice));
     HIPCHK(c, hipMemcpy(wsp<uint8_t>(c, c->L.off_fixed), F.data(), np, hipMemcpyHostToDevice));
     c->ncx = nc[0]; c->ncy = nc[1]; c->ncz = nc[2];
+    c->prmax = rmax;
+    HIPCHK(c, nl_reset(c));
     // forget the old footprint, then record bounding boxes for the first clear
     HIPCHK(c, launch_fill_u32(wsp<uint32_t>(c, c->L.off_nown), 0u, (int64_t)((c->L.N + 7) / 8 * 2), c->stream));
     HIPCHK(c, launch_fill_u32(wsp<uint32_t>(c, c->L.off_Fh), 0u, (int64_t)(3 * np * 2), c->stream));
@@ -950,6 +983,42 @@ int lbm_get_lattice_block(const lbm_ctx *c, int *threads, int *order, int *cu_gr
     return LBM_OK;
 }
 
+int lbm_set_neighbour_list(lbm_ctx *c, int every, double skin) {
+    if (!c) return LBM_E_INVALID;
+    if (every < 0) return fail(c, LBM_E_INVALID, "every must be >= 0");
+    if (every > 0 && !(skin > 0.0 && skin <= 2.0 * c->L.rmax))
+        return fail(c, LBM_E_INVALID, "skin must be in (0, 2 max_radius]");
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->side_stream));
+    const int old_every = c->nl_every;
+    const double old_skin = c->nl_skin;
+    c->nl_every = every;
+    if (every > 0) c->nl_skin = skin;
+    int nc[3];
+    cell_grid(c, c->np, c->prmax, nc);
+    if ((int64_t)nc[0] * nc[1] * nc[2] > c->L.cell_budget) {
+        c->nl_every = old_every;
+        c->nl_skin = old_skin;
+        return fail(c, LBM_E_INVALID, "cell grid above the reserved budget");
+    }
+    drop_graphs(c);  // captured steps hold the other contact kernels
+    c->ncx = nc[0]; c->ncy = nc[1]; c->ncz = nc[2];
+    HIPCHK(c, nl_reset(c));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return LBM_OK;
+}
+
+int lbm_get_neighbour_list(lbm_ctx *c, int *every, double *skin, int64_t *builds) {
+    if (!c) return LBM_E_INVALID;
+    if (every) *every = c->nl_every;
+    if (skin) *skin = c->nl_skin;
+    if (builds) {
+        HIPCHK(c, hipStreamSynchronize(c->side_stream));
+        HIPCHK(c, hipMemcpy(builds, c->ws + c->L.off_nl_state + 8, 8, hipMemcpyDeviceToHost));
+    }
+    return LBM_OK;
+}
+
 // Every launch shape computes the same bits at every node, so the choice is by
 // time alone: each candidate runs real steps with the lattice phase timed,
 // twice in opposite orders so that a drift of the clock or of the state
@@ -1112,6 +1181,8 @@ int lbm_load(lbm_ctx *c, const char *path) {
     HIPCHK(c, hipMemcpy(c->ws + c->L.off_fixed, fixed.data(), P, hipMemcpyHostToDevice));
     c->np = np;
     c->ncx = nc[0]; c->ncy = nc[1]; c->ncz = nc[2];
+    c->prmax = rmax;
+    HIPCHK(c, nl_reset(c));
     c->cur = 0;
     c->t = t;
     c->particles_set = true;
