@@ -78,12 +78,14 @@ def shape_text(shape):
     return "%d%s%s" % (width, "/xcd" if order == "xcd" else "", "/cu%d" % cap if cap else "")
 
 
-def run_variant(binding, inputs, w, parts, storage, steps, warmup, eps="sampling", block=None):
+def run_variant(binding, inputs, w, parts, storage, steps, warmup, eps="sampling", block=None, pipeline=None):
     import torch
     sim = binding.Simulation(w.dim, w.shape, w.tau, storage=storage, wall_y=w.wall_y,
                              fluid_force=w.fluid_force, particle_accel=w.particle_accel,
                              samples=w.samples, kn=w.kn, restitution=w.restitution,
                              max_particles=w.count, max_radius=w.radius, eps=eps)
+    if pipeline is not None:
+        sim.set_pipeline(pipeline)
     sim.set_particles(*parts)
     # the lattice kernel's workgroup width: measured per workload and storage
     # (part of the warm-up), or as given
@@ -105,31 +107,37 @@ def run_variant(binding, inputs, w, parts, storage, steps, warmup, eps="sampling
     lat_ms, lat_n = sim.get_timing()["lattice"]
     sim.set_timing(False)
     # per-phase breakdown from a short separate pass with events around every phase
+    phase_steps = min(steps, 50)
     sim.set_timing(True)
-    sim.step(min(steps, 50))
+    sim.step(phase_steps)
     phases = sim.get_timing()
     sim.set_timing(False)
+    slabs = sim.pipeline
     wall = t1 - t0
     mlups = w.nodes * steps / wall / 1e6
+    # one launch of the lattice kernel updates the whole lattice, or one slab
+    # of it when the slab pipeline is on (lat_n = steps x slabs)
     avg_ms = lat_ms / max(lat_n, 1)
+    launch_nodes = w.nodes * steps / max(lat_n, 1)
     Q = 9 if w.dim == 2 else 19
     bpn = 2 * Q * BYTES_PER_VALUE[storage]
-    achieved = bpn * w.nodes / (avg_ms * 1e-3) / 1e9
-    traffic = measured_traffic(storage, w.name, width)
+    achieved = bpn * launch_nodes / (avg_ms * 1e-3) / 1e9
+    traffic = measured_traffic(storage, w.name, width) if slabs == 1 else None
     step_gbs = bpn * mlups / 1e3
     sim.close()
     del sim
     torch.cuda.empty_cache()
     return {
         "mlups": mlups, "ms_per_step": wall / steps * 1e3, "wall_s": wall,
-        "lattice_kernel_ms": avg_ms, "bytes_per_node": bpn,
+        "lattice_kernel_ms": lat_ms / steps, "lattice_launch_ms": avg_ms, "lattice_launches_per_step": lat_n / steps,
+        "pipeline_slabs": slabs, "bytes_per_node": bpn,
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic},
         "roofline_step": {"bound": "hbm", "achieved": round(step_gbs, 1), "peak": HBM_PEAK_GBS,
                           "unit": "GB/s", "frac": round(step_gbs / HBM_PEAK_GBS, 4),
                           "basis": "whole step: MLUPS x %d B/node" % bpn},
-        "phase_ms_per_step": {k: round(v[0] / v[1], 4) for k, v in phases.items() if v[1] > 0},
+        "phase_ms_per_step": {k: round(v[0] / phase_steps, 4) for k, v in phases.items() if v[1] > 0},
         "lattice_block": width,
         "lattice_block_tuning_ms": None if tune_ms is None else {
             shape_text(k): round(v, 4) for k, v in tune_ms.items() if math.isfinite(v)},
@@ -330,6 +338,8 @@ def main():
                     help='lattice kernel launch shape: "auto" (measured per variant), a width '
                          '64/128/192/256 with an optional "/xcd" workgroup order and "/cuN" cap of '
                          'N workgroups per CU, or per variant, e.g. "fp64=256/xcd/cu3,fp32s=64"')
+    ap.add_argument("--pipeline", type=int, default=None,
+                    help="slab pipeline: 0 automatic, 1 off, 2..8 slabs (default: the library's)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-precision", action="store_true",
                     help="skip the FP32s / FP16 error measurement against the FP64 run")
@@ -358,10 +368,10 @@ def main():
     res = {}
     for v in variants:
         res[v] = run_variant(binding, inputs, w, parts, v, args.steps, args.warmup, eps=args.eps,
-                             block=blocks.get(v))
-        print("# %s: %.1f MLUPS, lattice kernel %.3f ms, %.1f GB/s, workgroup %s"
-              % (v, res[v]["mlups"], res[v]["lattice_kernel_ms"], res[v]["roofline"]["achieved"],
-                 res[v]["lattice_block"]), file=sys.stderr, flush=True)
+                             block=blocks.get(v), pipeline=args.pipeline)
+        print("# %s: %.1f MLUPS, lattice kernel %.3f ms per step (%d slabs), %.1f GB/s, workgroup %s"
+              % (v, res[v]["mlups"], res[v]["lattice_kernel_ms"], res[v]["pipeline_slabs"],
+                 res[v]["roofline"]["achieved"], res[v]["lattice_block"]), file=sys.stderr, flush=True)
     base = res["fp64"]
     out = {
         "metric": METRIC,
@@ -381,7 +391,7 @@ def main():
                       "walls y" if w.wall_y else "periodic", w.count,
                       "spheres" if w.dim == 3 else "discs", w.radius, round(w.tau, 4), w.rho_ratio),
                    "nodes": w.nodes, "particles": w.count, "storage": "fp64", "eps": args.eps,
-                   "lattice_block": base["lattice_block"],
+                   "lattice_block": base["lattice_block"], "pipeline_slabs": base["pipeline_slabs"],
                    "lattice_block_tuning_ms": base["lattice_block_tuning_ms"]},
         "roofline": base["roofline"],
         "roofline_step": base["roofline_step"],
@@ -390,7 +400,7 @@ def main():
                          "ms_per_step": round(r["ms_per_step"], 4),
                          "roofline": r["roofline"], "roofline_step": r["roofline_step"],
                          "phase_ms_per_step": r["phase_ms_per_step"],
-                         "lattice_block": r["lattice_block"],
+                         "lattice_block": r["lattice_block"], "pipeline_slabs": r["pipeline_slabs"],
                          "lattice_block_tuning_ms": r["lattice_block_tuning_ms"],
                          "speedup_vs_fp64": round(r["mlups"] / base["mlups"], 3)}
                      for v, r in res.items() if v != "fp64"},

@@ -226,6 +226,26 @@ int lbm_set_neighbour_list(lbm_ctx *ctx, int every, double skin);
  * of list builds so far (synchronises). */
 int lbm_get_neighbour_list(lbm_ctx *ctx, int *every, double *skin, int64_t *builds);
 
+/* Slab pipeline (lattices with walls in y and particles).  Every step of the
+ * method chains footprint -> lattice update (Eqs. 1-2) -> force and torque
+ * sums (Eq. 3) -> integration -> next footprint.  With K slabs the lattice
+ * update of a step runs slab by slab in y, and the particles whose footprint
+ * lies in slabs g - 1 .. g (with one node of margin for the step's motion)
+ * take their force sums, integration and next footprint on the side stream
+ * as soon as slab g is done, while the later slabs update; the next step's
+ * slab k waits only for groups k and k + 1.  Every particle and node runs the
+ * same arithmetic as in the plain step, so the results are the same bits.
+ * slabs: 1 off (a new context's default: on MI355X the overlapped particle
+ * kernels slow the lattice kernel by more than they hide), 0 automatic (4),
+ * 2..8 requested.  In use are at most as many slabs as keep every slab at
+ * least 2 R_max + 5 rows high, and one (the plain step) without walls in y or
+ * particles; lbm_get_pipeline gives the number in use.  Pipelined steps are
+ * launched one by one (never captured as a graph).  The pipeline needs every
+ * particle to move at most one node in y per step: a faster one raises
+ * LBM_E_NONFINITE at the step.  Errors: LBM_E_INVALID (slabs outside 0..8). */
+int lbm_set_pipeline(lbm_ctx *ctx, int slabs);
+int lbm_get_pipeline(const lbm_ctx *ctx, int *slabs);
+
 /* Chooses the lattice kernel's launch shape by measurement.  Each of the 24
  * candidates (width 64, 128, 192, 256 for k % 4 = 0..3, order (k / 4) % 2,
  * cap 0, 4, 3 workgroups per CU for k / 8 = 0..2; XCD candidates skipped

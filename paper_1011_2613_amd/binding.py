@@ -54,7 +54,7 @@ _SYMBOLS = ("lbm_workspace_bytes", "lbm_create", "lbm_destroy", "lbm_set_particl
             "lbm_get_contact_forces", "lbm_get_particles", "lbm_get_macro", "lbm_get_q",
             "lbm_time", "lbm_particle_count", "lbm_set_timing", "lbm_get_timing", "lbm_save", "lbm_load",
             "lbm_set_lattice_block", "lbm_get_lattice_block", "lbm_autotune_lattice_block", "lbm_get_stats",
-            "lbm_set_neighbour_list", "lbm_get_neighbour_list",
+            "lbm_set_neighbour_list", "lbm_get_neighbour_list", "lbm_set_pipeline", "lbm_get_pipeline",
             "lbm_error_string", "lbm_last_error",
             "mlp_workspace_bytes", "mlp_create", "mlp_destroy", "mlp_set_params", "mlp_get_params",
             "mlp_forward", "mlp_gradients", "mlp_train_step", "mlp_gradients_noalloc",
@@ -104,6 +104,8 @@ def load():
     L.lbm_get_stats.argtypes = [vp, C.POINTER(lbm_stats)]
     L.lbm_set_neighbour_list.argtypes = [vp, C.c_int, C.c_double]
     L.lbm_get_neighbour_list.argtypes = [vp, ip, dp, C.POINTER(i64)]
+    L.lbm_set_pipeline.argtypes = [vp, C.c_int]
+    L.lbm_get_pipeline.argtypes = [vp, ip]
     L.lbm_save.argtypes = [vp, C.c_char_p]
     L.lbm_load.argtypes = [vp, C.c_char_p]
     L.lbm_error_string.argtypes = [C.c_int]
@@ -323,6 +325,17 @@ class Simulation:
         e, s, b = C.c_int(0), C.c_double(0.0), C.c_int64(0)
         self._check(load().lbm_get_neighbour_list(self._ctx, C.byref(e), C.byref(s), C.byref(b)))
         return e.value, s.value, b.value
+
+    def set_pipeline(self, slabs):
+        """Slab pipeline: 0 automatic, 1 off, 2..8 slabs (lbm_set_pipeline)."""
+        self._check(load().lbm_set_pipeline(self._ctx, int(slabs)))
+
+    @property
+    def pipeline(self):
+        """Slabs in use (1: the plain step)."""
+        k = C.c_int(0)
+        self._check(load().lbm_get_pipeline(self._ctx, C.byref(k)))
+        return k.value
 
     def set_lattice_block(self, threads, order="linear", cu_groups=0):
         """Launch shape of the lattice kernel: workgroup width (0: built-in

@@ -40,6 +40,7 @@ enum : uint32_t {
     FLAG_CONTACT_OVERFLOW = 4u,
     FLAG_NONFINITE = 8u,
     FLAG_BATCH_TIMEOUT = 16u,
+    FLAG_FAST = 32u,       // a particle moved more than one node in y in a step (slab pipeline)
 };
 
 constexpr int MAX_OWNERS = 4;
@@ -123,7 +124,34 @@ struct LBArgs {
     float arel0f;
     float tauf;
     uint32_t *flags;
+    int y0, ny_run;        // rows y0 .. y0 + ny_run - 1 of every z plane (a slab; ny_run = ny: all)
 };
+
+// Slab pipeline (walls in y): the lattice update of a step runs slab by slab
+// in y; the particles whose footprint can reach no higher than slab g (with a
+// node of margin for the step's motion) form group g, whose force sums,
+// integration and next footprint run as soon as slabs g - 1 and g are done.
+constexpr int PIPE_MAX = 8;
+struct Groups {
+    const int *count;      // [K] particles of each group this step
+    const int *list;       // [K][P] their ids
+    int *ncount;           // [K] the next step's groups (filled by the integration)
+    int *nlist;            // [K][P]
+    int K;                 // slabs (1: no pipeline)
+    int g;                 // the group a launch takes; -1: every particle, one per workgroup
+    int stride;            // entries reserved per group list
+    int ys[PIPE_MAX + 1];  // slab k holds rows ys[k] .. ys[k + 1] - 1
+};
+
+// Group of a particle at height y with radius R: the slab that holds the
+// highest node its footprint can reach after one more step of at most one
+// node, floor(y + R + 3/2).
+__device__ __forceinline__ int slab_group(const Groups &G, double y, double R) {
+    const int top = (int)floor(y + R + 1.5);
+    int k = 0;
+    while (k + 1 < G.K && G.ys[k + 1] <= top) k++;
+    return k;
+}
 
 struct FootArgs {
     Particles P;
@@ -136,6 +164,7 @@ struct FootArgs {
     // bin width and the direction scales sqrt(2) NT and sqrt(3) NT
     const uint16_t *tab;
     double tabH, tabW, tabK1, tabK2;
+    Groups G;
 };
 
 struct ForceArgs {
@@ -146,6 +175,8 @@ struct ForceArgs {
     int D;
     int integrate;         // 1: the kernel also advances the particle (needs F^c of this step)
     double ap[3];          // particle acceleration (gravity with buoyancy)
+    uint32_t *flags;
+    Groups G;              // G.K > 1: the integration also files the particle in its next group
 };
 
 struct CellArgs {
@@ -282,6 +313,9 @@ hipError_t launch_stats(int lattice, int storage, const StatsArgs &a, hipStream_
 // launchers (particle_kernels.hip)
 hipError_t launch_foot_paint(const FootArgs &a, int D, hipStream_t s);
 hipError_t launch_force(const ForceArgs &a, hipStream_t s);
+// files every particle in its group of the current step (G.nlist / G.ncount
+// must be cleared first)
+hipError_t launch_assign_groups(const ForceArgs &a, hipStream_t s);
 hipError_t launch_list_q(const ForceArgs &a, double *out, hipStream_t s);
 hipError_t launch_cells(const CellArgs &a, hipStream_t s);
 hipError_t launch_dem(const CellArgs &a, hipStream_t s);

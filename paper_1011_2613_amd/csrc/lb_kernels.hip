@@ -378,6 +378,7 @@ __global__ __launch_bounds__(256) void k_lb(LBArgs a) {
     uint32_t xt;
     int y, z;
     tile_of<XO>(xt, y, z);
+    y += a.y0;  // the launch covers rows y0 .. y0 + ny_run - 1
     const int x = (int)xt * blockDim.x + threadIdx.x;
     if (x >= a.g.nx) return;
     const uint64_t n = (uint64_t)x + (uint64_t)a.g.nx * ((uint64_t)y + (uint64_t)a.g.ny * (uint64_t)z);
@@ -512,6 +513,7 @@ template <class L, int ST>
 static hipError_t lb_dispatch(const LBArgs &a, int width, int order, int cu_groups, hipStream_t s) {
     int block;
     dim3 grid = lattice_grid(a.g, block);
+    grid.y = (unsigned)a.ny_run;
     if (width > 0) {
         // a chosen workgroup width: part of one row per workgroup, the ragged
         // end of a row masked by the kernel's x < nx test

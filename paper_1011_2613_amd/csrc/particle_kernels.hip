@@ -193,12 +193,11 @@ __device__ __forceinline__ int eps_lookup(const FootArgs &a, double d0, double d
 // k-th covered node takes place k of the particle's list and an owner slot, so
 // the list is the same on every run.
 template <int D, int S, int NT, bool TAB>
-__global__ __launch_bounds__(NT) void k_foot_paint(FootArgs a) {
+__device__ __forceinline__ void foot_one(const FootArgs &a, int p) {
     constexpr int CHUNK = 1024;
     __shared__ uint16_t s_cnt[CHUNK];
     __shared__ uint16_t s_todo[CHUNK];
     __shared__ int s_ntodo;
-    const int p = blockIdx.x;
     const int P = a.P.np;
     int lo[3], hi[3];
     bbox(a.P, p, D, lo, hi);
@@ -352,6 +351,22 @@ __global__ __launch_bounds__(NT) void k_foot_paint(FootArgs a) {
     }
 }
 
+// Footprints of every particle (one workgroup each), or of the particles of
+// group G.g (workgroups walk the group's list).
+template <int D, int S, int NT, bool TAB>
+__global__ __launch_bounds__(NT) void k_foot_paint(FootArgs a) {
+    if (a.G.g < 0) {
+        foot_one<D, S, NT, TAB>(a, (int)blockIdx.x);
+        return;
+    }
+    const int n = a.G.count[a.G.g];
+    const int *lst = a.G.list + (int64_t)a.G.g * a.G.stride;
+    for (int i = (int)blockIdx.x; i < n; i += (int)gridDim.x) {
+        foot_one<D, S, NT, TAB>(a, lst[i]);
+        __syncthreads();  // the shared buffers are reused by the next particle
+    }
+}
+
 __device__ __forceinline__ double wrap_pos(double x, double L) {
     if (x < 0.0) {
         x = x + L;
@@ -395,12 +410,11 @@ __device__ __forceinline__ double shfl_xor_d(double v, int m) {
 // the first thread merges the wavefronts in a fixed order.
 // F_p = -sum, T_p = -sum.
 template <int D, bool R32, int NT>
-__global__ __launch_bounds__(NT) void k_force(ForceArgs a) {
+__device__ __forceinline__ void force_one(const ForceArgs &a, int p) {
     constexpr int nw = NT / 64;
     __shared__ double part[nw][12];
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
-    const int p = blockIdx.x;
     const int P = a.P.np;
     const int len = a.P.list_len[p];
     const int cap = a.P.list_cap;
@@ -560,8 +574,42 @@ __global__ __launch_bounds__(NT) void k_force(ForceArgs a) {
             } else {
                 a.P.w[2 * P + p] = pw[2] + Tv[2] / pI;
             }
+            // the slab pipeline assumes at most one node of motion in y per step
+            if (a.G.K > 1 && !(fabs(a.P.v[P + p]) <= 1.0)) atomicOr(a.flags, FLAG_FAST);
+        }
+        if (a.integrate && a.G.K > 1) {
+            // file the particle in its group of the next step
+            const int gn = slab_group(a.G, a.P.x[P + p], a.P.R[p]);
+            const int slot = atomicAdd(&a.G.ncount[gn], 1);
+            a.G.nlist[(int64_t)gn * a.G.stride + slot] = p;
         }
     }
+}
+
+// Force, torque and integration of every particle (one workgroup each), or
+// of the particles of group G.g (workgroups walk the group's list).
+template <int D, bool R32, int NT>
+__global__ __launch_bounds__(NT) void k_force(ForceArgs a) {
+    if (a.G.g < 0) {
+        force_one<D, R32, NT>(a, (int)blockIdx.x);
+        return;
+    }
+    const int n = a.G.count[a.G.g];
+    const int *lst = a.G.list + (int64_t)a.G.g * a.G.stride;
+    for (int i = (int)blockIdx.x; i < n; i += (int)gridDim.x) {
+        force_one<D, R32, NT>(a, lst[i]);
+        __syncthreads();  // the shared partial sums are reused by the next particle
+    }
+}
+
+// Files every particle in its group of the current positions.
+__global__ void k_assign_groups(ForceArgs a) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    const int P = a.P.np;
+    if (p >= P) return;
+    const int g = slab_group(a.G, a.P.x[P + p], a.P.R[p]);
+    const int slot = atomicAdd(&a.G.ncount[g], 1);
+    a.G.nlist[(int64_t)g * a.G.stride + slot] = p;
 }
 
 // q_n of the last step at the nodes of the current footprint lists (the nodes
@@ -880,9 +928,12 @@ __global__ void k_nl_finish(CellArgs a) {
 // ---------------------------------------------------------------- launchers
 static unsigned blocks_for(int n, int per) { return (unsigned)((n + per - 1) / per); }
 
+// workgroups of a launch that walks one group's list
+constexpr int GROUP_GRID = 4096;
+
 template <int D, int NT, bool TAB>
 static hipError_t paint_s(const FootArgs &a, hipStream_t s) {
-    const dim3 g((unsigned)a.P.np), b((unsigned)NT);
+    const dim3 g((unsigned)(a.G.g < 0 ? a.P.np : std::min(a.P.np, GROUP_GRID))), b((unsigned)NT);
     switch (a.S) {
         case 1: hipLaunchKernelGGL((k_foot_paint<D, 1, NT, TAB>), g, b, 0, s, a); break;
         case 2: hipLaunchKernelGGL((k_foot_paint<D, 2, NT, TAB>), g, b, 0, s, a); break;
@@ -907,7 +958,7 @@ hipError_t launch_foot_paint(const FootArgs &a, int D, hipStream_t s) {
 hipError_t launch_force(const ForceArgs &a, hipStream_t s) {
     if (a.P.np == 0) return hipSuccess;
     // one wavefront per particle
-    const dim3 g((unsigned)a.P.np), b(64);
+    const dim3 g((unsigned)(a.G.g < 0 ? a.P.np : std::min(a.P.np, GROUP_GRID))), b(64);
     if (a.D == 2) {
         if (a.rec32) hipLaunchKernelGGL((k_force<2, true, 64>), g, b, 0, s, a);
         else hipLaunchKernelGGL((k_force<2, false, 64>), g, b, 0, s, a);
@@ -915,6 +966,12 @@ hipError_t launch_force(const ForceArgs &a, hipStream_t s) {
         if (a.rec32) hipLaunchKernelGGL((k_force<3, true, 64>), g, b, 0, s, a);
         else hipLaunchKernelGGL((k_force<3, false, 64>), g, b, 0, s, a);
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_assign_groups(const ForceArgs &a, hipStream_t s) {
+    if (a.P.np == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_assign_groups, dim3(blocks_for(a.P.np, 256)), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 

@@ -39,7 +39,8 @@ struct Layout {
     size_t off_list, off_list_len;
     int list_cap;
     double rmax;
-    size_t off_cc, off_cid, off_flags, off_tab, off_stats, off_nl, off_nl_len, off_xb, off_nl_state, total;
+    size_t off_cc, off_cid, off_flags, off_tab, off_stats, off_nl, off_nl_len, off_xb, off_nl_state;
+    size_t off_gcount, off_glist, list_buf, total;
 };
 
 int validate(const lbm_config *c, std::string &msg) {
@@ -95,13 +96,21 @@ Layout make_layout(const lbm_config *c) {
     L.off_Fh = take(3 * P * 8);
     L.off_Th = take(3 * P * 8);
     L.off_Fc = take(3 * P * 8);
-    L.off_bb = take(6 * P * 4);
-    // footprint list: every node of the bounding box of the largest particle
+    // footprint records of two steps (the current and the last completed
+    // one: the slab pipeline paints the next footprint before a step ends):
+    // bounding boxes, lists of every node of the bounding box of the largest
+    // particle, list lengths; buffer k starts k * list_buf bytes after the first
     L.rmax = c->max_radius > 0.0 ? c->max_radius : 8.0;
     const int ext = (int)std::floor(2.0 * L.rmax + 1.0) + 1;
     L.list_cap = L.D == 2 ? ext * ext : ext * ext * ext;
-    L.off_list = take(P * (size_t)L.list_cap * 4);
-    L.off_list_len = take(P * 4);
+    {
+        const size_t o0 = o;
+        L.off_bb = take(6 * P * 4);
+        L.off_list = take(P * (size_t)L.list_cap * 4);
+        L.off_list_len = take(P * 4);
+        L.list_buf = o - o0;
+        o += L.list_buf;
+    }
     L.off_cc = take((size_t)L.cell_budget * 4);
     L.off_cid = take((size_t)L.cell_budget * CELL_CAP * 4);
     L.off_flags = take(64);
@@ -113,6 +122,9 @@ Layout make_layout(const lbm_config *c) {
     L.off_nl_len = take(P * 4);
     L.off_xb = take(3 * P * 8);
     L.off_nl_state = take(64);
+    // slab pipeline: group counts and lists of two steps
+    L.off_gcount = take(2 * PIPE_MAX * 4);
+    L.off_glist = take(2 * (size_t)PIPE_MAX * P * 4);
     L.total = o;
     return L;
 }
@@ -134,7 +146,8 @@ struct lbm_ctx {
     // footprint, lattice and force kernels (they only read positions and
     // velocities, which change in the integration at the end of the step)
     hipStream_t side_stream;
-    hipEvent_t ev_fork[2], ev_join[2];
+    static constexpr int GS = 8;  // event slots (steps in flight at once in the pipeline)
+    hipEvent_t ev_fork[GS], ev_join[GS], ev_L[GS][PIPE_MAX], ev_P[GS][PIPE_MAX];
     int cur;  // 0: state in fA, 1: state in fB
     int64_t t;
     int np;
@@ -149,6 +162,8 @@ struct lbm_ctx {
     int lb_width;  // lattice kernel workgroup width, 0 for the built-in rule
     int lb_order;  // lattice kernel workgroup order, LBM_ORDER_LINEAR / _XCD
     int lb_cu_groups;  // lattice kernel workgroups per CU at most, 0: no cap
+    int pipe_req;      // slab pipeline requested: 0 automatic, 1 off, 2..PIPE_MAX slabs
+    int pipe_K;        // slabs in use (1: the plain step)
     int nl_every;      // 0: cell list every step; else neighbour lists, rebuilt after nl_every steps at most
     double nl_skin;    // list margin beyond contact
     double prmax;      // largest radius of the current particles
@@ -182,7 +197,10 @@ int fail(lbm_ctx *c, int code, const char *fmt, ...) {
         if (e_ != hipSuccess) return fail(ctx, LBM_E_HIP, "%s: %s", #expr, hipGetErrorString(e_)); \
     } while (0)
 
-Particles particles(lbm_ctx *c) {
+// Particle arrays with the footprint records of buffer `buf` (a step's
+// footprint lives in the buffer of its state parity).
+Particles particles(lbm_ctx *c, int buf) {
+    const size_t fb = (size_t)buf * c->L.list_buf;
     Particles P;
     P.x = wsp<double>(c, c->L.off_x);
     P.v = wsp<double>(c, c->L.off_v);
@@ -194,9 +212,9 @@ Particles particles(lbm_ctx *c) {
     P.Fh = wsp<double>(c, c->L.off_Fh);
     P.Th = wsp<double>(c, c->L.off_Th);
     P.Fc = wsp<double>(c, c->L.off_Fc);
-    P.bb = wsp<int>(c, c->L.off_bb);
-    P.list = wsp<uint32_t>(c, c->L.off_list);
-    P.list_len = wsp<int>(c, c->L.off_list_len);
+    P.bb = wsp<int>(c, c->L.off_bb + fb);
+    P.list = wsp<uint32_t>(c, c->L.off_list + fb);
+    P.list_len = wsp<int>(c, c->L.off_list_len + fb);
     P.list_cap = c->L.list_cap;
     P.np = c->np;
     return P;
@@ -241,7 +259,7 @@ bool particle_ok(const lbm_ctx *c, double r, const double *pos, const double *ve
 
 CellArgs cell_args(lbm_ctx *c) {
     CellArgs a;
-    a.P = particles(c);
+    a.P = particles(c, c->cur);  // positions and velocities only
     a.g = c->g;
     a.ncx = c->ncx; a.ncy = c->ncy; a.ncz = c->ncz;
     a.cell_count = wsp<int>(c, c->L.off_cc);
@@ -272,9 +290,74 @@ hipError_t nl_reset(lbm_ctx *c) {
     return e;
 }
 
-FootArgs foot_args(lbm_ctx *c) {
+// Slab-pipeline groups of the step reading state `from`: this step's group
+// lists (filled by the previous step's integration) and the next step's.
+Groups groups_of(lbm_ctx *c, int from, int g) {
+    Groups G;
+    const size_t stride = (size_t)c->L.P;
+    int *cnt = wsp<int>(c, c->L.off_gcount);
+    int *lst = wsp<int>(c, c->L.off_glist);
+    G.count = cnt + from * PIPE_MAX;
+    G.list = lst + (size_t)from * PIPE_MAX * stride;
+    G.ncount = cnt + (1 - from) * PIPE_MAX;
+    G.nlist = lst + (size_t)(1 - from) * PIPE_MAX * stride;
+    G.K = c->pipe_K;
+    G.g = g;
+    G.stride = (int)stride;
+    for (int k = 0; k <= PIPE_MAX; k++)
+        G.ys[k] = k <= c->pipe_K ? (int)((int64_t)c->g.ny * k / c->pipe_K) : c->g.ny;
+    return G;
+}
+
+// Footprint arguments painting into buffer `buf`; G.g = -1: every particle.
+FootArgs foot_args(lbm_ctx *c, int buf, const Groups &G);
+ForceArgs force_args(lbm_ctx *c, int buf, const Groups &G);
+void drop_graphs(lbm_ctx *c);
+
+// Slabs of the pipeline for the current particles: 1 (the plain step) without
+// walls in y, without particles or when switched off; otherwise the requested
+// number (4 when automatic), reduced until every slab is at least
+// 2 R_max + 5 rows high (a particle's footprint then spans two slabs at most,
+// also after a step of one node).
+int resolve_pipe(const lbm_ctx *c) {
+    if (!c->g.wall_y || c->np == 0 || c->pipe_req == 1) return 1;
+    const int want = c->pipe_req == 0 ? 4 : c->pipe_req;
+    const int minh = (int)std::ceil(2.0 * c->prmax) + 5;
+    const int k = std::min(want, c->g.ny / std::max(minh, 1));
+    return std::max(1, std::min(k, PIPE_MAX));
+}
+
+// Brings the footprint of the coming step in line with the slab count
+// resolve_pipe gives (stream-ordered on the context's stream).  The pipeline
+// paints a step's footprint during the step before, the plain step at its
+// start; the owner counts are zero at the start of a plain step.
+hipError_t pipe_setup(lbm_ctx *c) {
+    const int K = resolve_pipe(c);
+    hipError_t e = hipSuccess;
+    if (c->pipe_K > 1 && K == 1) {  // painted ahead: forget it
+        e = launch_fill_u32(wsp<uint32_t>(c, c->L.off_nown), 0u, (int64_t)((c->L.N + 7) / 8 * 2), c->stream);
+    }
+    // from the plain step: paint the coming step's footprint; to another
+    // slab count: file the particles in the new groups
+    const bool paint = K > 1 && c->pipe_K == 1;
+    const bool regroup = K > 1 && K != c->pipe_K;
+    if (K != c->pipe_K) drop_graphs(c);
+    c->pipe_K = K;
+    const int from = c->cur;
+    if (e == hipSuccess && regroup) {
+        const Groups G = groups_of(c, 1 - from, -1);  // its ncount / nlist are step `from`'s lists
+        e = launch_fill_u32((uint32_t *)G.ncount, 0u, PIPE_MAX, c->stream);
+        if (e == hipSuccess) e = launch_assign_groups(force_args(c, from, G), c->stream);
+    }
+    if (e == hipSuccess && paint)  // into the buffer of the step's parity
+        e = launch_foot_paint(foot_args(c, from, groups_of(c, from, -1)), c->L.D, c->stream);
+    return e;
+}
+
+FootArgs foot_args(lbm_ctx *c, int buf, const Groups &G) {
     FootArgs a;
-    a.P = particles(c);
+    a.G = G;
+    a.P = particles(c, buf);
     a.g = c->g;
     a.nown = wsp<uint8_t>(c, c->L.off_nown);
     a.slots = wsp<uint32_t>(c, c->L.off_slots);
@@ -366,7 +449,24 @@ LBArgs lb_args(lbm_ctx *c, int from) {
     a.arel0f = (float)c->arel0;
     a.tauf = (float)c->cfg.tau;
     a.flags = flags(c);
+    a.y0 = 0;
+    a.ny_run = c->g.ny;
     return a;
+}
+
+// Force-kernel arguments reading the footprint of buffer `buf`.
+ForceArgs force_args(lbm_ctx *c, int buf, const Groups &G) {
+    ForceArgs fo;
+    fo.P = particles(c, buf);
+    fo.g = c->g;
+    fo.qr = wsp<char>(c, c->L.off_qr);
+    fo.rec32 = c->cfg.storage != LBM_FP64;
+    fo.D = c->L.D;
+    fo.integrate = 1;
+    for (int d = 0; d < 3; d++) fo.ap[d] = c->cfg.particle_accel[d];
+    fo.flags = flags(c);
+    fo.G = G;
+    return fo;
 }
 
 // Phase markers for the timing mode.
@@ -390,9 +490,11 @@ void phase_end(lbm_ctx *c, hipStream_t s) {
     c->ev_used++;
 }
 
-// Queue one complete time step reading state `from`.  `slot` selects the
-// fork/join event pair (two steps are captured per graph).
-hipError_t enqueue_step(lbm_ctx *c, int from, hipStream_t s, int slot) {
+// Queue one complete time step reading state `from` (the plain schedule):
+// footprint, lattice, force and integration on stream s, the DEM on the side
+// stream joined before the force kernel.  `slot` selects the step's events
+// (up to GS steps are captured per graph).
+hipError_t enqueue_plain(lbm_ctx *c, int from, hipStream_t s, int slot) {
     hipError_t e;
     const int lattice = c->cfg.lattice, storage = c->cfg.storage;
     if (c->np > 0) {
@@ -407,7 +509,7 @@ hipError_t enqueue_step(lbm_ctx *c, int from, hipStream_t s, int slot) {
         if ((e = c->nl_every > 0 ? launch_nl_contacts(ca, d) : launch_dem(ca, d)) != hipSuccess) return e;
         phase_end(c, d);
         if ((e = hipEventRecord(c->ev_join[slot], d)) != hipSuccess) return e;
-        FootArgs fa = foot_args(c);
+        FootArgs fa = foot_args(c, from, groups_of(c, from, -1));
         phase_begin(c, 0, s);
         if ((e = launch_foot_paint(fa, c->L.D, s)) != hipSuccess) return e;
         phase_end(c, s);
@@ -416,14 +518,7 @@ hipError_t enqueue_step(lbm_ctx *c, int from, hipStream_t s, int slot) {
     if ((e = launch_lb(lattice, storage, lb_args(c, from), c->lb_width, c->lb_order, c->lb_cu_groups, s)) != hipSuccess) return e;
     phase_end(c, s);
     if (c->np > 0) {
-        ForceArgs fo;
-        fo.P = particles(c);
-        fo.g = c->g;
-        fo.qr = wsp<char>(c, c->L.off_qr);
-        fo.rec32 = c->cfg.storage != LBM_FP64;
-        fo.D = c->L.D;
-        fo.integrate = 1;
-        for (int d = 0; d < 3; d++) fo.ap[d] = c->cfg.particle_accel[d];
+        ForceArgs fo = force_args(c, from, groups_of(c, from, -1));
         // the force kernel integrates: it needs the contact forces; the cell
         // list and the contacts overlap the footprint and lattice kernels
         if ((e = hipStreamWaitEvent(s, c->ev_join[slot], 0)) != hipSuccess) return e;
@@ -434,6 +529,110 @@ hipError_t enqueue_step(lbm_ctx *c, int from, hipStream_t s, int slot) {
     return hipSuccess;
 }
 
+// Queue one time step of the slab pipeline (walls in y, K slabs) on two
+// streams.  Stream s runs the lattice slabs in order; slab k of step t waits
+// for the particle groups k and k + 1 of step t - 1 (their new footprints lie
+// in slabs up to k + 1; slab k rewrites rows that the step-(t - 1) slabs
+// k - 1 .. k + 1 read, which stream order already covers).  The side stream
+// runs, in order, the DEM of step t (it needs every particle's position at t:
+// the last group of step t - 1 precedes it on this stream) and then each
+// group g (force and torque sums of step t, integration, filing into the
+// next step's groups, footprint of step t + 1) once slab g is done (slab
+// g - 1 precedes it on s).  `first`: no step of this schedule is pending (the
+// side stream then also waits for the work queued on s before the step);
+// `last`: join the side stream back into s at the end.  The footprint of step
+// t was painted by step t - 1 (or by the set-up) into buffer `from`.
+hipError_t enqueue_pipe(lbm_ctx *c, int from, hipStream_t s, int slot, bool first, bool last) {
+    hipError_t e;
+    const int K = c->pipe_K;
+    const int prev = (slot + lbm_ctx::GS - 1) % lbm_ctx::GS;
+    hipStream_t d = c->side_stream;
+    const int lattice = c->cfg.lattice, storage = c->cfg.storage;
+    if (first) {
+        if ((e = hipEventRecord(c->ev_fork[slot], s)) != hipSuccess) return e;
+        if ((e = hipStreamWaitEvent(d, c->ev_fork[slot], 0)) != hipSuccess) return e;
+    }
+    CellArgs ca = cell_args(c);
+    phase_begin(c, 3, d);
+    if ((e = c->nl_every > 0 ? launch_nl_rebuild(ca, d) : launch_cells(ca, d)) != hipSuccess) return e;
+    phase_end(c, d);
+    phase_begin(c, 4, d);
+    if ((e = c->nl_every > 0 ? launch_nl_contacts(ca, d) : launch_dem(ca, d)) != hipSuccess) return e;
+    phase_end(c, d);
+    // the next step's groups are filed from empty (after the previous step's
+    // groups, which read these counts, on this stream)
+    const Groups G0 = groups_of(c, from, -1);
+    if ((e = launch_fill_u32((uint32_t *)G0.ncount, 0u, PIPE_MAX, d)) != hipSuccess) return e;
+    for (int k = 0; k < K; k++) {
+        if (!first) {
+            if ((e = hipStreamWaitEvent(s, c->ev_P[prev][k], 0)) != hipSuccess) return e;
+            if (k + 1 < K && (e = hipStreamWaitEvent(s, c->ev_P[prev][k + 1], 0)) != hipSuccess) return e;
+        }
+        LBArgs la = lb_args(c, from);
+        la.y0 = G0.ys[k];
+        la.ny_run = G0.ys[k + 1] - G0.ys[k];
+        phase_begin(c, 1, s);
+        if ((e = launch_lb(lattice, storage, la, c->lb_width, c->lb_order, c->lb_cu_groups, s)) != hipSuccess)
+            return e;
+        phase_end(c, s);
+        if ((e = hipEventRecord(c->ev_L[slot][k], s)) != hipSuccess) return e;
+    }
+    for (int g = 0; g < K; g++) {
+        if ((e = hipStreamWaitEvent(d, c->ev_L[slot][g], 0)) != hipSuccess) return e;
+        const Groups G = groups_of(c, from, g);
+        ForceArgs fo = force_args(c, from, G);
+        phase_begin(c, 2, d);
+        if ((e = launch_force(fo, d)) != hipSuccess) return e;
+        phase_end(c, d);
+        FootArgs fa = foot_args(c, 1 - from, G);
+        phase_begin(c, 0, d);
+        if ((e = launch_foot_paint(fa, c->L.D, d)) != hipSuccess) return e;
+        phase_end(c, d);
+        if ((e = hipEventRecord(c->ev_P[slot][g], d)) != hipSuccess) return e;
+    }
+    if (last) {
+        if ((e = hipEventRecord(c->ev_join[slot], d)) != hipSuccess) return e;
+        if ((e = hipStreamWaitEvent(s, c->ev_join[slot], 0)) != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+hipError_t enqueue_step(lbm_ctx *c, int from, hipStream_t s, int slot, bool first, bool last) {
+    if (c->pipe_K > 1 && c->np > 0) return enqueue_pipe(c, from, s, slot, first, last);
+    return enqueue_plain(c, from, s, slot);
+}
+
+// The step events (fork/join, lattice slabs, particle groups) of every
+// slot; events that were not created are null.
+bool create_step_events(lbm_ctx *c) {
+    bool ok = true;
+    auto mk = [&](hipEvent_t &ev) {
+        ev = nullptr;
+        if (ok) ok = hipEventCreateWithFlags(&ev, hipEventDisableTiming) == hipSuccess;
+    };
+    for (int k = 0; k < lbm_ctx::GS; k++) {
+        mk(c->ev_fork[k]);
+        mk(c->ev_join[k]);
+        for (int g = 0; g < PIPE_MAX; g++) {
+            mk(c->ev_L[k][g]);
+            mk(c->ev_P[k][g]);
+        }
+    }
+    return ok;
+}
+
+void destroy_step_events(lbm_ctx *c) {
+    auto rm = [](hipEvent_t ev) { if (ev) (void)hipEventDestroy(ev); };
+    for (int k = 0; k < lbm_ctx::GS; k++) {
+        rm(c->ev_fork[k]);
+        rm(c->ev_join[k]);
+        for (int g = 0; g < PIPE_MAX; g++) {
+            rm(c->ev_L[k][g]);
+            rm(c->ev_P[k][g]);
+        }
+    }
+}
+
 void drop_graphs(lbm_ctx *c) {
     for (int k = 0; k < 2; k++) {
         if (c->graph_ok[k]) (void)hipGraphExecDestroy(c->graph[k]);
@@ -441,13 +640,18 @@ void drop_graphs(lbm_ctx *c) {
     }
 }
 
+// Steps per captured graph of the plain schedule (one A -> B -> A swap, so the
+// state parity returns to `from`).
+constexpr int GRAPH_STEPS = 2;
+
 int build_graph(lbm_ctx *c, int from) {
     hipGraph_t graph;
     HIPCHK(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
-    hipError_t e1 = enqueue_step(c, from, c->cap_stream, 0);
-    hipError_t e2 = e1 == hipSuccess ? enqueue_step(c, 1 - from, c->cap_stream, 1) : e1;
+    hipError_t e1 = hipSuccess;
+    for (int k = 0; k < GRAPH_STEPS && e1 == hipSuccess; k++)
+        e1 = enqueue_plain(c, (from + k) & 1, c->cap_stream, k);
     hipError_t e3 = hipStreamEndCapture(c->cap_stream, &graph);
-    if (e2 != hipSuccess) return fail(c, LBM_E_HIP, "graph capture: %s", hipGetErrorString(e2));
+    if (e1 != hipSuccess) return fail(c, LBM_E_HIP, "graph capture: %s", hipGetErrorString(e1));
     if (e3 != hipSuccess) return fail(c, LBM_E_HIP, "graph capture end: %s", hipGetErrorString(e3));
     hipError_t e4 = hipGraphInstantiate(&c->graph[from], graph, nullptr, nullptr, 0);
     (void)hipGraphDestroy(graph);
@@ -467,6 +671,8 @@ int check_flags(lbm_ctx *c) {
     if (h[0] & FLAG_CONTACT_OVERFLOW)
         return fail(c, LBM_E_CONTACT_OVERFLOW, "a particle has more than %d contacts", MAX_CONTACTS);
     if (h[0] & FLAG_NONFINITE) return fail(c, LBM_E_NONFINITE, "non-finite value in the state or a particle outside the box");
+    if (h[0] & FLAG_FAST)
+        return fail(c, LBM_E_NONFINITE, "a particle moved more than one node in y in one step (slab pipeline)");
     return LBM_OK;
 }
 
@@ -570,6 +776,8 @@ int lbm_create(const lbm_config *cfg, void *workspace, size_t ws_bytes, void *hi
     c->nl_every = 0;
     c->nl_skin = 1.0;
     c->prmax = 0.0;
+    c->pipe_req = 1;  // off: measured slower than the plain step on MI355X
+    c->pipe_K = 1;
     c->rec_open = false;
     c->ev_used = 0;
     for (int k = 0; k < LBM_NPHASES; k++) { c->phase_ms[k] = 0.0; c->phase_n[k] = 0; }
@@ -583,18 +791,12 @@ int lbm_create(const lbm_config *cfg, void *workspace, size_t ws_bytes, void *hi
         delete c;
         return fail(nullptr, LBM_E_HIP, "hipStreamCreateWithFlags failed");
     }
-    {
-        bool ok = true;
-        for (int k = 0; k < 2; k++) {
-            ok = ok && hipEventCreateWithFlags(&c->ev_fork[k], hipEventDisableTiming) == hipSuccess;
-            ok = ok && hipEventCreateWithFlags(&c->ev_join[k], hipEventDisableTiming) == hipSuccess;
-        }
-        if (!ok) {
-            (void)hipStreamDestroy(c->side_stream);
-            (void)hipStreamDestroy(c->cap_stream);
-            delete c;
-            return fail(nullptr, LBM_E_HIP, "hipEventCreateWithFlags failed");
-        }
+    if (!create_step_events(c)) {
+        destroy_step_events(c);
+        (void)hipStreamDestroy(c->side_stream);
+        (void)hipStreamDestroy(c->cap_stream);
+        delete c;
+        return fail(nullptr, LBM_E_HIP, "hipEventCreateWithFlags failed");
     }
     // beta(eps) (Eq. 2) and (1 - beta)/tau for every possible clamped count
     std::vector<double> beta(L.Smax + 1), arel(L.Smax + 1);
@@ -626,10 +828,7 @@ int lbm_create(const lbm_config *cfg, void *workspace, size_t ws_bytes, void *hi
     }
     chk(hipStreamSynchronize(c->stream));
     if (r != LBM_OK) {
-        for (int k = 0; k < 2; k++) {
-            (void)hipEventDestroy(c->ev_fork[k]);
-            (void)hipEventDestroy(c->ev_join[k]);
-        }
+        destroy_step_events(c);
         (void)hipStreamDestroy(c->side_stream);
         (void)hipStreamDestroy(c->cap_stream);
         delete c;
@@ -648,10 +847,7 @@ void lbm_destroy(lbm_ctx *c) {
         (void)hipEventDestroy(e.b);
     }
     (void)hipStreamSynchronize(c->side_stream);
-    for (int k = 0; k < 2; k++) {
-        (void)hipEventDestroy(c->ev_fork[k]);
-        (void)hipEventDestroy(c->ev_join[k]);
-    }
+    destroy_step_events(c);
     (void)hipStreamDestroy(c->side_stream);
     (void)hipStreamDestroy(c->cap_stream);
     delete c;
@@ -777,11 +973,15 @@ int lbm_set_particles(lbm_ctx *c, int64_t n, const double *pos, const double *ve
     HIPCHK(c, launch_fill_u32(wsp<uint32_t>(c, c->L.off_Fh), 0u, (int64_t)(3 * np * 2), c->stream));
     HIPCHK(c, launch_fill_u32(wsp<uint32_t>(c, c->L.off_Th), 0u, (int64_t)(3 * np * 2), c->stream));
     HIPCHK(c, launch_fill_u32(wsp<uint32_t>(c, c->L.off_Fc), 0u, (int64_t)(3 * np * 2), c->stream));
-    HIPCHK(c, launch_fill_u32(wsp<uint32_t>(c, c->L.off_list_len), 0u, (int64_t)np, c->stream));
+    for (int b = 0; b < 2; b++)
+        HIPCHK(c, launch_fill_u32(wsp<uint32_t>(c, c->L.off_list_len + (size_t)b * c->L.list_buf), 0u,
+                                  (int64_t)np, c->stream));
     // a new particle set starts with clear health flags
     HIPCHK(c, launch_fill_u32(flags(c), 0u, 16, c->stream));
-    HIPCHK(c, hipStreamSynchronize(c->stream));
     c->particles_set = true;
+    c->pipe_K = 1;  // the footprint is forgotten: set the pipeline up afresh
+    HIPCHK(c, pipe_setup(c));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
     return LBM_OK;
 }
 
@@ -839,7 +1039,7 @@ int lbm_get_q(lbm_ctx *c, double *q, int ptr_kind) {
     const size_t bytes = (size_t)c->L.D * c->L.N * 8;
     return produce_to(c, q, bytes, ptr_kind, [&](void *dst) {
         ForceArgs fo;
-        fo.P = particles(c);
+        fo.P = particles(c, 1 - c->cur);  // the last completed step's footprint
         fo.g = c->g;
         fo.qr = wsp<char>(c, c->L.off_qr);
         fo.rec32 = c->cfg.storage != LBM_FP64;
@@ -900,34 +1100,41 @@ int lbm_step(lbm_ctx *c, int64_t nsteps) {
         return fail(c, LBM_E_STATE, "lbm_step before lbm_set_particles (n may be 0) or lbm_load");
     if (nsteps == 0) return LBM_OK;
     hipError_t e;
-    if (c->timing) {
-        for (int64_t k = 0; k < nsteps; k++) {
-            if ((e = enqueue_step(c, c->cur, c->stream, 0)) != hipSuccess)
+    constexpr int GS = lbm_ctx::GS;
+    // steps queued one by one (timing mode, or the steps beyond whole graphs)
+    auto eager = [&](int64_t n) -> int {
+        for (int64_t k = 0; k < n; k++) {
+            if ((e = enqueue_step(c, c->cur, c->stream, (int)(k % GS), k == 0, k == n - 1)) != hipSuccess)
                 return fail(c, LBM_E_HIP, "step: %s", hipGetErrorString(e));
             c->cur ^= 1;
             c->t++;
         }
+        return LBM_OK;
+    };
+    // The slab pipeline always launches step by step: its three-stream
+    // schedule is not captured as a graph (its capture crashed the host
+    // runtime once and is switched off); a step's launches take far less host
+    // time than the step takes on the GPU, so the queue stays ahead.
+    if (c->timing || (c->pipe_K > 1 && c->np > 0)) {
+        const int r = eager(nsteps);
+        if (r != LBM_OK) return r;
         return check_flags(c);
     }
     int64_t left = nsteps;
-    if (left >= 2) {
+    if (left >= GRAPH_STEPS) {
         if (!c->graph_ok[c->cur]) {
             int r = build_graph(c, c->cur);
             if (r != LBM_OK) return r;
         }
-        const int64_t pairs = left / 2;
-        for (int64_t k = 0; k < pairs; k++)
+        const int64_t reps = left / GRAPH_STEPS;
+        for (int64_t k = 0; k < reps; k++)
             if ((e = hipGraphLaunch(c->graph[c->cur], c->stream)) != hipSuccess)
                 return fail(c, LBM_E_HIP, "graph launch: %s", hipGetErrorString(e));
-        c->t += 2 * pairs;
-        left -= 2 * pairs;
+        c->t += GRAPH_STEPS * reps;
+        left -= GRAPH_STEPS * reps;
     }
-    if (left == 1) {
-        if ((e = enqueue_step(c, c->cur, c->stream, 0)) != hipSuccess)
-            return fail(c, LBM_E_HIP, "step: %s", hipGetErrorString(e));
-        c->cur ^= 1;
-        c->t++;
-    }
+    const int r = eager(left);
+    if (r != LBM_OK) return r;
     return check_flags(c);
 }
 
@@ -1016,6 +1223,24 @@ int lbm_get_neighbour_list(lbm_ctx *c, int *every, double *skin, int64_t *builds
         HIPCHK(c, hipStreamSynchronize(c->side_stream));
         HIPCHK(c, hipMemcpy(builds, c->ws + c->L.off_nl_state + 8, 8, hipMemcpyDeviceToHost));
     }
+    return LBM_OK;
+}
+
+int lbm_set_pipeline(lbm_ctx *c, int slabs) {
+    if (!c) return LBM_E_INVALID;
+    if (slabs < 0 || slabs > PIPE_MAX) return fail(c, LBM_E_INVALID, "slabs must be in 0..%d", PIPE_MAX);
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    c->pipe_req = slabs;
+    if (c->particles_set) {
+        HIPCHK(c, pipe_setup(c));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+    }
+    return LBM_OK;
+}
+
+int lbm_get_pipeline(const lbm_ctx *c, int *slabs) {
+    if (!c || !slabs) return LBM_E_INVALID;
+    *slabs = c->pipe_K;
     return LBM_OK;
 }
 
@@ -1187,8 +1412,12 @@ int lbm_load(lbm_ctx *c, const char *path) {
     c->t = t;
     c->particles_set = true;
     HIPCHK(c, launch_fill_u32(wsp<uint32_t>(c, c->L.off_nown), 0u, (int64_t)((c->L.N + 7) / 8 * 2), c->stream));
-    HIPCHK(c, launch_fill_u32(wsp<uint32_t>(c, c->L.off_list_len), 0u, (int64_t)P, c->stream));
+    for (int b = 0; b < 2; b++)
+        HIPCHK(c, launch_fill_u32(wsp<uint32_t>(c, c->L.off_list_len + (size_t)b * c->L.list_buf), 0u,
+                                  (int64_t)P, c->stream));
     HIPCHK(c, launch_fill_u32(flags(c), 0u, 16, c->stream));
+    c->pipe_K = 1;  // the footprint is forgotten: set the pipeline up afresh
+    HIPCHK(c, pipe_setup(c));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     return LBM_OK;
 }
@@ -1199,7 +1428,7 @@ int lbm_get_stats(lbm_ctx *c, lbm_stats *out) {
     StatsArgs a;
     a.A = state(c, c->cur);
     a.g = c->g;
-    a.P = particles(c);
+    a.P = particles(c, 1 - c->cur);  // the last completed step's footprint
     a.qr = wsp<char>(c, c->L.off_qr);
     a.rec32 = c->cfg.storage != LBM_FP64;
     a.Smax = c->L.Smax;

@@ -327,7 +327,7 @@ def test_lattice_block_autotune(gpu_lib):
     t = a.get_timing()
     assert all(n == 0 for _, n in t.values())   # counters cleared, mode kept
     a.step(5)
-    assert a.get_timing()["lattice"][1] == 5
+    assert a.get_timing()["lattice"][1] == 5 * a.pipeline  # one launch per slab
     a.set_timing(False)
     a.step(6)
     b = gpu_lib.Simulation(3, box, 0.65, **kw)
