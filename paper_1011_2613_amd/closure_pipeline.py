@@ -13,6 +13,7 @@ lattice step, force sum and network evaluation runs in the HIP library.
 import argparse
 import json
 import math
+import os
 import time
 
 import numpy as np
@@ -62,6 +63,37 @@ def run_ensemble(boxes, samples=4, max_steps=20000, check_every=500, tol=1e-5, t
     return X, y, box_of, row_steady, stats
 
 
+def _cache_name(seed, n_boxes, max_steps, tol):
+    return "ensemble_s%d_b%d_m%d_t%g.npz" % (seed, n_boxes, max_steps, tol)
+
+
+def cached_ensemble(seed, n_boxes, dirs, save_dir, budget_end=None, **kw):
+    """The dataset of the ensemble of `n_boxes` boxes drawn from `seed`: read
+    from the first of `dirs` that holds it, else run (and saved into
+    `save_dir` when given).  Returns None, without running, when the wall
+    clock is past `budget_end`."""
+    name = _cache_name(seed, n_boxes, kw.get("max_steps", 20000), kw.get("tol", 1e-5))
+    for d in dirs:
+        path = os.path.join(d, name)
+        if os.path.exists(path):
+            z = np.load(path)
+            st = json.loads(str(z["stats"]))
+            st["cached"] = True
+            return z["X"], z["y"], z["box_of"], z["row_steady"], st
+    if budget_end is not None and time.time() > budget_end:
+        return None
+    boxes = E.sample_boxes(n_boxes, seed)
+    X, y, box_of, rs, st = run_ensemble(boxes, **kw)
+    st.pop("raw")
+    if save_dir:
+        os.makedirs(save_dir, exist_ok=True)
+        tmp = os.path.join(save_dir, name + ".tmp.npz")
+        np.savez_compressed(tmp, X=X, y=y, box_of=box_of, row_steady=rs, stats=json.dumps(st, default=lambda o: o.item() if hasattr(o, "item") else str(o)))
+        os.replace(tmp, os.path.join(save_dir, name))
+    st["cached"] = False
+    return X, y, box_of, rs, st
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--ensembles", type=int, default=2)
@@ -76,6 +108,13 @@ def main(argv=None):
     ap.add_argument("--infer-rows", type=int, default=1 << 20)
     ap.add_argument("--out", default=None)
     ap.add_argument("--tune-cache", default=None, help="JSON file of tuned tile shapes (read and written)")
+    ap.add_argument("--data-dirs", default="",
+                    help="comma-separated folders searched for ensembles run before (one npz each)")
+    ap.add_argument("--save-dir", default=None, help="folder the ensembles run here are saved into")
+    ap.add_argument("--collect-only", action="store_true",
+                    help="run (or find) the ensembles only: no training or evaluation")
+    ap.add_argument("--budget-s", type=float, default=None,
+                    help="start no new ensemble after this many seconds")
     ap.add_argument("--save-raw", default=None,
                     help="npz file for the raw results (box parameters, mean velocities, particle "
                          "positions, shell velocities and forces) of every ensemble")
@@ -84,30 +123,45 @@ def main(argv=None):
     if not torch.cuda.is_available():
         raise SystemExit("closure pipeline: no GPU visible")
 
+    t_start = time.time()
+    budget_end = t_start + args.budget_s if args.budget_s else None
+    dirs = [d for d in args.data_dirs.split(",") if d] + ([args.save_dir] if args.save_dir else [])
+    run_kw = dict(max_steps=args.max_steps, check_every=args.check_every, tol=args.tol, tune_cache=args.tune_cache)
     Xs, ys, ens_stats, raws = [], [], [], []
     for e in range(args.ensembles):
-        boxes = E.sample_boxes(args.boxes, 1000 + e)
-        say("ensemble %d: %d boxes" % (e, len(boxes)))
-        X, y, _, rs, st = run_ensemble(boxes, max_steps=args.max_steps, check_every=args.check_every,
-                                       tol=args.tol, tune_cache=args.tune_cache)
+        if args.save_raw:
+            boxes = E.sample_boxes(args.boxes, 1000 + e)
+            X, y, _, rs, st = run_ensemble(boxes, **run_kw)
+            raws.append(st.pop("raw"))
+            st["cached"] = False
+        else:
+            got = cached_ensemble(1000 + e, args.boxes, dirs, args.save_dir, budget_end, **run_kw)
+            if got is None:
+                say("ensemble %d: time budget spent, stopping" % e)
+                break
+            X, y, _, rs, st = got
         X, y = X[rs], y[rs]  # train on steady drag only
-        say("  steady %d/%d boxes, %d samples, %.1f s, %.0f MLUPS"
-            % (st["steady_boxes"], st["boxes"], st["samples"], st["run_s"], st["mlups"]))
+        say("ensemble %d: steady %d/%d boxes, %d samples, %.1f s, %.0f MLUPS%s"
+            % (e, st["steady_boxes"], st["boxes"], st["samples"], st["run_s"], st["mlups"],
+               " (cached)" if st["cached"] else ""))
         Xs.append(X)
         ys.append(y)
-        raws.append(st.pop("raw"))
         ens_stats.append(st)
+    if args.collect_only:
+        say("collected %d ensembles, %d samples" % (len(ys), sum(len(v) for v in ys)))
+        return {"ensembles": len(ys), "samples": int(sum(len(v) for v in ys))}
     Xtr, ytr = np.concatenate(Xs), np.concatenate(ys)
 
-    test_boxes = E.sample_boxes(args.heldout, 9000)
-    say("held-out: %d boxes" % len(test_boxes))
-    Xall, yall, ball, rste, test_stats = run_ensemble(test_boxes, max_steps=args.max_steps,
-                                                      check_every=args.check_every, tol=args.tol,
-                                                      tune_cache=args.tune_cache)
+    say("held-out: %d boxes" % args.heldout)
+    if args.save_raw:
+        test_boxes = E.sample_boxes(args.heldout, 9000)
+        Xall, yall, ball, rste, test_stats = run_ensemble(test_boxes, **run_kw)
+        raw_test = test_stats.pop("raw")
+    else:
+        Xall, yall, ball, rste, test_stats = cached_ensemble(9000, args.heldout, dirs, args.save_dir, **run_kw)
     Xte, yte, bte = Xall[rste], yall[rste], ball[rste]
     say("  steady %d/%d boxes, %d samples (%d in boxes not steady by the step cap)"
         % (test_stats["steady_boxes"], test_stats["boxes"], test_stats["samples"], test_stats["unsteady_samples"]))
-    raw_test = test_stats.pop("raw")
     if args.save_raw:
         arrs = {}
         for i, r in enumerate(raws + [raw_test]):

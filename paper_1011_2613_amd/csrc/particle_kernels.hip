@@ -779,6 +779,59 @@ __global__ __launch_bounds__(256) void k_dem(CellArgs a) {
     }
 }
 
+// One thread per particle, for many particles (k_dem keeps a wavefront busy
+// with 9 or 27 neighbour cells, most of its lanes idle in 2D): the thread
+// walks the neighbour cells itself and inserts each touching neighbour into
+// its own id-sorted column of LDS, then adds the pair forces in ascending id
+// and the walls, the sum order of k_dem, so both kernels give the same bits.
+template <int NT>
+__global__ __launch_bounds__(NT) void k_dem_thread(CellArgs a) {
+    __shared__ int list[MAX_CONTACTS][NT];
+    const int t = threadIdx.x;
+    const int i = blockIdx.x * NT + t;
+    const int P = a.P.np;
+    const int D = a.D;
+    if (i >= P) return;  // no barrier below
+    const int c0 = cell_coord(a, 0, a.P.x[i]);
+    const int c1 = cell_coord(a, 1, a.P.x[P + i]);
+    const int c2 = D == 3 ? cell_coord(a, 2, a.P.x[2 * P + i]) : 0;
+    int ox[3], oy[3], oz[3];
+    const int nxc = axis_cells(c0, a.ncx, true, ox);
+    const int nyc = axis_cells(c1, a.ncy, !a.g.wall_y, oy);
+    int nzc = 1;
+    oz[0] = 0;
+    if (D == 3) nzc = axis_cells(c2, a.ncz, true, oz);
+    int nl = 0;
+    bool overflow = false;
+    for (int kz = 0; kz < nzc; kz++)
+        for (int ky = 0; ky < nyc; ky++)
+            for (int kx = 0; kx < nxc; kx++) {
+                const int c = ox[kx] + a.ncx * (oy[ky] + a.ncy * oz[kz]);
+                const int cnt = min(a.cell_count[c], CELL_CAP);
+                for (int s = 0; s < cnt; s++) {
+                    const int j = a.cell_ids[c * CELL_CAP + s];
+                    if (j == i) continue;
+                    if (!pair_force(a, i, j, nullptr)) continue;
+                    if (nl >= MAX_CONTACTS) {
+                        overflow = true;
+                        continue;
+                    }
+                    int q = nl;
+                    while (q > 0 && list[q - 1][t] > j) {
+                        list[q][t] = list[q - 1][t];
+                        q--;
+                    }
+                    list[q][t] = j;
+                    nl++;
+                }
+            }
+    if (overflow) atomicOr(a.flags, FLAG_CONTACT_OVERFLOW);
+    double F[3] = {0.0, 0.0, 0.0};
+    for (int s = 0; s < nl; s++) pair_force(a, i, list[s][t], F);
+    wall_force(a, i, F);
+    for (int d = 0; d < 3; d++) a.P.Fc[d * P + i] = F[d];
+}
+
 // ------------------------------------------------------ neighbour-list mode
 // The lists hold, in ascending id, every j with |r_i - r_j| < R_i + R_j + skin
 // (minimum image) at the last build.  A pair missing from the lists was at
@@ -947,12 +1000,23 @@ static hipError_t paint_s(const FootArgs &a, hipStream_t s) {
     return hipGetLastError();
 }
 
+// Threads per particle of the footprint kernel (compile-time knobs for
+// measurement).  Measured on MI355X at 4^D samples: a disc of radius 5 runs
+// fastest with one wavefront (1.3-1.4x faster than two; four are slower
+// still), a sphere of radius 4 with two (one or four are slower).
+#ifndef FOOT_NT2
+#define FOOT_NT2 64
+#endif
+#ifndef FOOT_NT3
+#define FOOT_NT3 128
+#endif
+
 hipError_t launch_foot_paint(const FootArgs &a, int D, hipStream_t s) {
     if (a.P.np == 0) return hipSuccess;
-    // two wavefronts per particle (measured faster than four); the table
-    // lookup is a kernel of its own, so the sampling kernel keeps its registers
-    if (a.tab) return D == 2 ? paint_s<2, 128, true>(a, s) : paint_s<3, 128, true>(a, s);
-    return D == 2 ? paint_s<2, 128, false>(a, s) : paint_s<3, 128, false>(a, s);
+    // the table lookup is a kernel of its own, so the sampling kernel keeps
+    // its registers
+    if (a.tab) return D == 2 ? paint_s<2, FOOT_NT2, true>(a, s) : paint_s<3, FOOT_NT3, true>(a, s);
+    return D == 2 ? paint_s<2, FOOT_NT2, false>(a, s) : paint_s<3, FOOT_NT3, false>(a, s);
 }
 
 hipError_t launch_force(const ForceArgs &a, hipStream_t s) {
@@ -991,9 +1055,20 @@ hipError_t launch_cells(const CellArgs &a, hipStream_t s) {
     return hipGetLastError();
 }
 
+// Contacts: a thread per particle for 2D runs of at least DEM_THREAD_MIN
+// discs, else a wavefront per particle.  Measured on MI355X: 21 361 discs
+// 25 against 65 us, 1 166 400 discs 0.54 against 4.4 ms; 8 317 spheres 168
+// against 26 us (too few wavefronts to hide a thread's walk over 27 cells).
+#ifndef DEM_THREAD_MIN
+#define DEM_THREAD_MIN 16384
+#endif
+
 hipError_t launch_dem(const CellArgs &a, hipStream_t s) {
     if (a.P.np == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_dem, dim3(blocks_for(a.P.np, 4)), dim3(256), 0, s, a);
+    if (a.D == 2 && a.P.np >= DEM_THREAD_MIN)
+        hipLaunchKernelGGL(k_dem_thread<128>, dim3(blocks_for(a.P.np, 128)), dim3(128), 0, s, a);
+    else
+        hipLaunchKernelGGL(k_dem, dim3(blocks_for(a.P.np, 4)), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 
