@@ -347,11 +347,18 @@ def main():
                     help="skip the FP32s / FP16 error measurement against the FP64 run")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the batched-ensemble and closure measurements")
+    ap.add_argument("--closure-only", action="store_true",
+                    help="only time the closure's inference kernel (4 M rows; for counter runs)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 2 GiB device copy (counter calibration)")
     args = ap.parse_args()
     if args.copy_calibration:
         copy_calibration()
+        return
+    if args.closure_only:
+        from paper_1011_2613_amd import binding
+        binding.load()
+        print(json.dumps({"closure": closure_bench(binding, rows=1 << 22)}), flush=True)
         return
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
