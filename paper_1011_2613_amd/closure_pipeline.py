@@ -124,7 +124,7 @@ def main(argv=None):
         raise SystemExit("closure pipeline: no GPU visible")
 
     t_start = time.time()
-    budget_end = t_start + args.budget_s if args.budget_s else None
+    budget_end = t_start + args.budget_s if args.budget_s is not None else None
     dirs = [d for d in args.data_dirs.split(",") if d] + ([args.save_dir] if args.save_dir else [])
     run_kw = dict(max_steps=args.max_steps, check_every=args.check_every, tol=args.tol, tune_cache=args.tune_cache)
     Xs, ys, ens_stats, raws = [], [], [], []

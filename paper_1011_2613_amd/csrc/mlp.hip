@@ -84,11 +84,13 @@ struct FwdArgs {
     float *z1, *z2, *z3;
 };
 
-// One dense layer for a 16-row tile held in LDS (row stride SIN): the NT
-// output tiles of 16 columns, acc[nt] = in W[16 nt .. 16 nt + 15]^T.  The
-// reduction index is outermost, so one A fragment feeds NT independent MFMA
-// chains; each output element still accumulates its K/32 products in
-// ascending order.
+// One dense layer for a 16-row tile held in LDS (row stride SIN), computed
+// transposed: acc[mt] = W[16 mt .. 16 mt + 15] in^T, so that a lane's four
+// results are four consecutive output features of one row (row l mod 16,
+// features 16 mt + 4 (l / 16) + i) and go to LDS as one 8-byte write.  The
+// reduction index is outermost, so one fragment of the input feeds NT
+// independent MFMA chains; each output element still accumulates its K/32
+// products in ascending order.
 template <int K, int SIN, int SW, int NT>
 __device__ __forceinline__ void layer_tiles(const __bf16 *sin, const __bf16 *sw, f32x4 (&acc)[NT]) {
     const int l = threadIdx.x & 63;
@@ -96,18 +98,19 @@ __device__ __forceinline__ void layer_tiles(const __bf16 *sin, const __bf16 *sw,
     for (int nt = 0; nt < NT; nt++) acc[nt] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
     for (int kt = 0; kt < K / 32; kt++) {
-        const bf16x8 a = *(const bf16x8 *)(sin + (l & 15) * SIN + kt * 32 + 8 * (l >> 4));
+        const bf16x8 x = *(const bf16x8 *)(sin + (l & 15) * SIN + kt * 32 + 8 * (l >> 4));
 #pragma unroll
         for (int nt = 0; nt < NT; nt++) {
-            const bf16x8 b = *(const bf16x8 *)(sw + (nt * 16 + (l & 15)) * SW + kt * 32 + 8 * (l >> 4));
-            acc[nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[nt], 0, 0, 0);
+            const bf16x8 w = *(const bf16x8 *)(sw + (nt * 16 + (l & 15)) * SW + kt * 32 + 8 * (l >> 4));
+            acc[nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w, x, acc[nt], 0, 0, 0);
         }
     }
 }
 
-// Forward workgroup: FWD_WAVES wavefronts share the bfloat16 weights in LDS;
-// each wavefront owns one activation tile (16 rows) that every layer
-// overwrites in place once its products are in registers.
+// Forward workgroup: FWD_WAVES wavefronts share the bfloat16 weights, the
+// hidden biases and the input normaliser in LDS; each wavefront owns one
+// activation tile (16 rows) that every layer overwrites in place once its
+// products are in registers.
 constexpr int FWD_WAVES = 12;
 constexpr int FWD_WAVES_TRAIN = 8;  // training also streams activations out
 
@@ -119,6 +122,8 @@ __global__ __launch_bounds__(TRAIN ? 64 * FWD_WAVES_TRAIN : 64 * FWD_WAVES) void
     __shared__ __attribute__((aligned(16))) __bf16 sW3[NH * SH];
     __shared__ __attribute__((aligned(16))) __bf16 sW4[16 * SH];
     __shared__ __attribute__((aligned(16))) __bf16 sAct[FWD_WAVES][16 * SH];
+    __shared__ __attribute__((aligned(16))) float sBias[3 * NH];
+    __shared__ float sMu[NIN], sRsd[NIN];
     const int tid = threadIdx.x, l = tid & 63, wv = tid >> 6;
     // weights -> LDS, 8 bf16 per copy
     for (int c = tid; c < NH * KIN / 8; c += blockDim.x) {
@@ -134,6 +139,16 @@ __global__ __launch_bounds__(TRAIN ? 64 * FWD_WAVES_TRAIN : 64 * FWD_WAVES) void
         const int r = c / (NH / 8), k = (c % (NH / 8)) * 8;
         *(bf16x8 *)(sW4 + r * SH + k) = *(const bf16x8 *)(a.w.w4 + r * NH + k);
     }
+    for (int c = tid; c < 3 * NH; c += blockDim.x) {
+        const int layer = c / NH, col = c % NH;
+        sBias[c] = a.p[(layer == 0 ? OFF_B1 : (layer == 1 ? OFF_B2 : OFF_B3)) + col];
+    }
+    const bool norm = !TRAIN && a.nmu;
+    if (norm)
+        for (int k = tid; k < NIN; k += blockDim.x) {
+            sMu[k] = a.nmu[k];
+            sRsd[k] = 1.0f / a.nsd[k];
+        }
     __syncthreads();
     __bf16 *buf = sAct[wv];
     const int64_t ntiles = (a.n + 15) / 16;
@@ -152,15 +167,18 @@ __global__ __launch_bounds__(TRAIN ? 64 * FWD_WAVES_TRAIN : 64 * FWD_WAVES) void
     float xv[XL];
     int64_t tile = (int64_t)blockIdx.x * NWV + wv;
     if (!TRAIN) load_tile(tile, xv);
+    // this lane's row of a tile and the first of its four features
+    const int lr = l & 15, lf = 4 * (l >> 4);
     for (; tile < ntiles; tile += (int64_t)gridDim.x * NWV) {
         const int64_t r0 = tile * 16;
+        const bool row_in = r0 + lr < a.n;
         if (TRAIN) load_tile(tile, xv);
         // input tile: 16 rows x 64 (40 features, zero padded), binary32 -> bfloat16
 #pragma unroll
         for (int j = 0; j < XL; j++) {
             const int idx = j * 64 + l, r = idx / NIN, k = idx % NIN;
             float xk = xv[j];
-            if (!TRAIN && a.nmu && r0 + r < a.n) xk = (xk - a.nmu[k]) / a.nsd[k];
+            if (norm && r0 + r < a.n) xk = (xk - sMu[k]) * sRsd[k];
             const __bf16 q = (__bf16)xk;
             buf[r * S1 + k] = q;
             if (TRAIN && r0 + r < a.n) a.h0[(r0 + r) * KIN + k] = q;
@@ -175,7 +193,6 @@ __global__ __launch_bounds__(TRAIN ? 64 * FWD_WAVES_TRAIN : 64 * FWD_WAVES) void
         // hidden layers
 #pragma unroll
         for (int layer = 0; layer < 3; layer++) {
-            const float *bias = a.p + (layer == 0 ? OFF_B1 : (layer == 1 ? OFF_B2 : OFF_B3));
             __bf16 *hg = layer == 0 ? a.h1 : (layer == 1 ? a.h2 : a.h3);
             float *zg = layer == 0 ? a.z1 : (layer == 1 ? a.z2 : a.z3);
             f32x4 acc[NH / 16];
@@ -184,33 +201,30 @@ __global__ __launch_bounds__(TRAIN ? 64 * FWD_WAVES_TRAIN : 64 * FWD_WAVES) void
             wave_sync();  // every lane's reads of the input tile are done
 #pragma unroll
             for (int nt = 0; nt < NH / 16; nt++) {
-                const int col = nt * 16 + (l & 15);
-                const float b = bias[col];
+                const int f0 = nt * 16 + lf;
+                const f32x4 b = *(const f32x4 *)(sBias + layer * NH + f0);
+                f32x4 z;
+                __bf16 h[4];
 #pragma unroll
                 for (int i = 0; i < 4; i++) {
-                    const int r = 4 * (l >> 4) + i;
-                    const float z = acc[nt][i] + b;
-                    const __bf16 h = (__bf16)silu_fwd(z);
-                    buf[r * SH + col] = h;
-                    if (TRAIN && r0 + r < a.n) {
-                        zg[(r0 + r) * NH + col] = z;
-                        hg[(r0 + r) * NH + col] = h;
-                    }
+                    z[i] = acc[nt][i] + b[i];
+                    h[i] = (__bf16)silu_fwd(z[i]);
+                }
+                typedef __attribute__((__vector_size__(4 * sizeof(__bf16)))) __bf16 bf16x4;
+                const bf16x4 hv = {h[0], h[1], h[2], h[3]};
+                *(bf16x4 *)(buf + lr * SH + f0) = hv;
+                if (TRAIN && row_in) {
+                    *(f32x4 *)(zg + (r0 + lr) * NH + f0) = z;
+                    *(bf16x4 *)(hg + (r0 + lr) * NH + f0) = hv;
                 }
             }
             wave_sync();
         }
-        // output layer: W4 padded to 16 rows, column 0 of the result is y
+        // output layer: W4 padded to 16 rows; output feature 0 of row l
+        // (l < 16) is y
         f32x4 acc[1];
         layer_tiles<NH, SH, SH, 1>(buf, sW4, acc);
-        if ((l & 15) == 0) {
-            const float b4 = a.p[OFF_B4];
-#pragma unroll
-            for (int i = 0; i < 4; i++) {
-                const int64_t row = r0 + 4 * (l >> 4) + i;
-                if (row < a.n) a.y[row] = acc[0][i] + b4;
-            }
-        }
+        if (l < 16 && row_in) a.y[r0 + l] = acc[0][0] + a.p[OFF_B4];
         wave_sync();
     }
 }
