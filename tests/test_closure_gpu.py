@@ -36,4 +36,8 @@ def test_closure_pipeline_small():
     const = float(np.mean(np.abs(np.exp(np.mean(np.log(ytr))) - yte) / yte))
     say("held-out:", res, "constant-predictor error %.3f" % const)
     assert res["mlp_rel_err_mean_all_rows"] < const
-    assert res["mlp_rel_err_mean_all_rows"] < res["wen_yu_rel_err_mean"]
+    # 450 training particles: a gain over the Wen-Yu-type correlation and a
+    # stated bound (the recorded 40-ensemble run is checked by
+    # test_closure_record.py)
+    assert res["mlp_rel_err_mean_all_rows"] < 0.8 * res["wen_yu_rel_err_mean"]
+    assert res["mlp_rel_err_mean_all_rows"] < 0.35
