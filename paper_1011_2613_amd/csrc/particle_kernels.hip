@@ -270,19 +270,18 @@ __device__ __forceinline__ void foot_one(const FootArgs &a, int p) {
         }
         __syncthreads();
         // (C1) the covered nodes of the chunk in node order into s_todo (the
-        // queue of (B) is spent): each thread takes PER consecutive nodes, one
+        // queue of (B) is spent): each thread takes ceil(nc / NT) consecutive
+        // nodes of the chunk (a disc's box fills a seventh of a chunk), one
         // workgroup prefix sum places them
         {
-            constexpr int PER = CHUNK / NT;
-            const int j0 = (int)threadIdx.x * PER;
+            const int per = (nc + NT - 1) / NT;
+            const int j0 = min((int)threadIdx.x * per, nc), j1 = min(j0 + per, nc);
             int m = 0;
-#pragma unroll
-            for (int u = 0; u < PER; u++) m += (j0 + u < nc && s_cnt[j0 + u] > 0) ? 1 : 0;
+            for (int j = j0; j < j1; j++) m += s_cnt[j] > 0 ? 1 : 0;
             int ncov;
             int at = block_scan(m, ncov);
-#pragma unroll
-            for (int u = 0; u < PER; u++)
-                if (j0 + u < nc && s_cnt[j0 + u] > 0) s_todo[at++] = (uint16_t)(j0 + u);
+            for (int j = j0; j < j1; j++)
+                if (s_cnt[j] > 0) s_todo[at++] = (uint16_t)j;
             __syncthreads();
             // (C2) owner slots and list entries, k-th covered node in lane
             // order.  Covered nodes that fall in one aligned 8-byte word of the
