@@ -401,64 +401,66 @@ __device__ __forceinline__ double shfl_xor_d(double v, int m) {
     return __shfl_xor(v, m, 64);
 }
 
-// One workgroup per particle over its footprint list: each entry gives the
-// node and the particle's sample count there; q_n and the node's total count
-// come from the lattice kernel.  With `integrate` set, the first thread then
-// advances the particle (the contact forces of the step are complete).  s_pn q_n and r_pn x (s_pn q_n) go into TwoSum
-// accumulators; each wavefront merges its lanes with butterfly shuffles and
-// the first thread merges the wavefronts in a fixed order.
-// F_p = -sum, T_p = -sum.
-template <int D, bool R32, int NT>
-__device__ __forceinline__ void force_one(const ForceArgs &a, int p) {
-    constexpr int nw = NT / 64;
-    __shared__ double part[nw][12];
+// LPP lanes of a wavefront per particle over its footprint list: each entry
+// gives the node and the particle's sample count there; q_n and the node's
+// total count come from the lattice kernel.  With `integrate` set, the
+// group's first lane then advances the particle (the contact forces of the
+// step are complete).  s_pn q_n and r_pn x (s_pn q_n) go into TwoSum
+// accumulators, which the group's lanes merge with butterfly shuffles.
+// F_p = -sum, T_p = -sum.  `sub` is the lane's index in its group (groups are
+// aligned runs of LPP lanes); `live` is false for the groups past the last
+// particle, which take part in the shuffles only.
+template <int D, bool R32, int LPP>
+__device__ __forceinline__ void force_lanes(const ForceArgs &a, int p, int sub, bool live) {
+    static_assert(LPP >= 16 && LPP <= 64 && (LPP & (LPP - 1)) == 0, "lanes per particle");
     const int lane = threadIdx.x & 63;
-    const int wave = threadIdx.x >> 6;
+    const int gbase = lane - sub;
     const int P = a.P.np;
-    const int len = a.P.list_len[p];
+    const int q = live ? p : 0;
+    const int len = live ? a.P.list_len[q] : 0;
     const int cap = a.P.list_cap;
-    const int lo0 = a.P.bb[p], lo1 = a.P.bb[P + p], lo2 = a.P.bb[2 * P + p];
-    const uint32_t *list = a.P.list + (int64_t)p * cap;
-    const double xp0 = a.P.x[p], xp1 = a.P.x[P + p], xp2 = D == 3 ? a.P.x[2 * P + p] : 0.0;
-    // the integration inputs, one per lane (v, omega, F^c, m, I, fixed),
-    // loaded beside the sums and gathered by the first thread at the end
+    const int lo0 = a.P.bb[q], lo1 = a.P.bb[P + q], lo2 = a.P.bb[2 * P + q];
+    const uint32_t *list = a.P.list + (int64_t)q * cap;
+    const double xp0 = a.P.x[q], xp1 = a.P.x[P + q], xp2 = D == 3 ? a.P.x[2 * P + q] : 0.0;
+    // the integration inputs, one per lane of the group (v, omega, F^c, m, I,
+    // fixed), loaded beside the sums and gathered by the first lane at the end
     double pre = 0.0;
-    if (a.integrate && lane < 12) {
-        if (lane < 3) pre = a.P.v[lane * P + p];
-        else if (lane < 6) pre = a.P.w[(lane - 3) * P + p];
-        else if (lane < 9) pre = a.P.Fc[(lane - 6) * P + p];
-        else if (lane == 9) pre = a.P.m[p];
-        else if (lane == 10) pre = a.P.I[p];
+    if (live && a.integrate && sub < 12) {
+        if (sub < 3) pre = a.P.v[sub * P + p];
+        else if (sub < 6) pre = a.P.w[(sub - 3) * P + p];
+        else if (sub < 9) pre = a.P.Fc[(sub - 6) * P + p];
+        else if (sub == 9) pre = a.P.m[p];
+        else if (sub == 10) pre = a.P.I[p];
         else pre = a.P.fixed[p] ? 1.0 : 0.0;
     }
     Acc F[3] = {{0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}};
     Acc T[3] = {{0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}};
-    // UN entries per thread per round: all q loads of a round are issued
+    // UN entries per lane per round: all q loads of a round are issued
     // before the first accumulation, and the list entries of the next round
     // are loaded while they are in flight (the first round's beside the list
     // length: loads below the capacity stay inside the particle's list).
-    constexpr int UN = 2;  // 80 registers: six wavefronts per SIMD
-    const int stride = UN * NT;
+    constexpr int UN = 2;
+    const int stride = UN * LPP;
     uint32_t vn[UN];
 #pragma unroll
     for (int u = 0; u < UN; u++) {
-        const int e = u * NT + (int)threadIdx.x;
+        const int e = u * LPP + sub;
         vn[u] = e < cap ? list[e] : 0u;
     }
+    // lattice coordinates of an entry, formed again where needed (fewer
+    // registers live across the loads)
+    auto coords = [&](uint32_t e, int &ix, int &iy, int &iz) {
+        ix = wrap1(a.g, 0, lo0 + (int)((e >> 10) & 127u));
+        iy = wrap1(a.g, 1, lo1 + (int)((e >> 17) & 127u));
+        iz = D == 3 ? wrap1(a.g, 2, lo2 + (int)((e >> 24) & 127u)) : 0;
+    };
     for (int e0 = 0; e0 < len; e0 += stride) {
         uint32_t v[UN];
 #pragma unroll
         for (int u = 0; u < UN; u++) {
-            const int e = e0 + u * NT + (int)threadIdx.x;
+            const int e = e0 + u * LPP + sub;
             v[u] = e < len ? vn[u] : 0u;
         }
-        // lattice coordinates of an entry, formed again where needed (fewer
-        // registers live across the loads)
-        auto coords = [&](uint32_t e, int &ix, int &iy, int &iz) {
-            ix = wrap1(a.g, 0, lo0 + (int)((e >> 10) & 127u));
-            iy = wrap1(a.g, 1, lo1 + (int)((e >> 17) & 127u));
-            iz = D == 3 ? wrap1(a.g, 2, lo2 + (int)((e >> 24) & 127u)) : 0;
-        };
         double q0[UN], q1[UN], q2[UN];
         int tot[UN];
 #pragma unroll
@@ -478,7 +480,7 @@ __device__ __forceinline__ void force_one(const ForceArgs &a, int p) {
         }
 #pragma unroll
         for (int u = 0; u < UN; u++) {
-            const int e = e0 + stride + u * NT + (int)threadIdx.x;
+            const int e = e0 + stride + u * LPP + sub;
             vn[u] = e < len ? list[e] : 0u;
         }
 #pragma unroll
@@ -487,7 +489,11 @@ __device__ __forceinline__ void force_one(const ForceArgs &a, int p) {
             const int cnt = (int)(v[u] & LIST_COUNT_MASK);
             int ix, iy, iz;
             coords(v[u], ix, iy, iz);
-            const double sh = (double)cnt / (double)tot[u];
+            // the particle's share of the node: exactly 1 where it is the
+            // only owner (cnt = tot), the division only where a wavefront
+            // holds a shared node
+            double sh = 1.0;
+            if (__any(cnt != tot[u]) && cnt != tot[u]) sh = (double)cnt / (double)tot[u];
             const double t0 = sh * q0[u], t1 = sh * q1[u];
             const double rx = ndisp(a.g, 0, ix, xp0);
             const double ry = ndisp(a.g, 1, iy, xp1);
@@ -505,45 +511,34 @@ __device__ __forceinline__ void force_one(const ForceArgs &a, int p) {
             }
         }
     }
+    // butterfly over the group's lanes: the components that can be nonzero
+    // (2D: F_x, F_y and T_z; the others stay zero and are not used)
 #pragma unroll
-    for (int m = 32; m >= 1; m >>= 1) {
+    for (int m = LPP / 2; m >= 1; m >>= 1) {
 #pragma unroll
         for (int d = 0; d < 3; d++) {
             Acc o;
-            o.s = shfl_xor_d(F[d].s, m);
-            o.c = shfl_xor_d(F[d].c, m);
-            acc_merge(F[d], o);
-            o.s = shfl_xor_d(T[d].s, m);
-            o.c = shfl_xor_d(T[d].c, m);
-            acc_merge(T[d], o);
-        }
-    }
-    if (lane == 0)
-        for (int d = 0; d < 3; d++) {
-            part[wave][2 * d] = F[d].s;
-            part[wave][2 * d + 1] = F[d].c;
-            part[wave][6 + 2 * d] = T[d].s;
-            part[wave][6 + 2 * d + 1] = T[d].c;
-        }
-    __syncthreads();
-    double pv[3], pw[3], pfc[3];
-    for (int d = 0; d < 3; d++) {
-        pv[d] = __shfl(pre, d, 64);
-        pw[d] = __shfl(pre, 3 + d, 64);
-        pfc[d] = __shfl(pre, 6 + d, 64);
-    }
-    const double pm = __shfl(pre, 9, 64), pI = __shfl(pre, 10, 64), pfix = __shfl(pre, 11, 64);
-    if (threadIdx.x == 0) {
-        for (int w = 1; w < nw; w++)
-            for (int d = 0; d < 3; d++) {
-                Acc o;
-                o.s = part[w][2 * d];
-                o.c = part[w][2 * d + 1];
+            if (d < D) {
+                o.s = shfl_xor_d(F[d].s, m);
+                o.c = shfl_xor_d(F[d].c, m);
                 acc_merge(F[d], o);
-                o.s = part[w][6 + 2 * d];
-                o.c = part[w][6 + 2 * d + 1];
+            }
+            if (D == 3 || d == 2) {
+                o.s = shfl_xor_d(T[d].s, m);
+                o.c = shfl_xor_d(T[d].c, m);
                 acc_merge(T[d], o);
             }
+        }
+    }
+    double pv[3], pw[3], pfc[3];
+    for (int d = 0; d < 3; d++) {
+        pv[d] = __shfl(pre, gbase + d, 64);
+        pw[d] = __shfl(pre, gbase + 3 + d, 64);
+        pfc[d] = __shfl(pre, gbase + 6 + d, 64);
+    }
+    const double pm = __shfl(pre, gbase + 9, 64), pI = __shfl(pre, gbase + 10, 64);
+    const double pfix = __shfl(pre, gbase + 11, 64);
+    if (live && sub == 0) {
         double Fv[3], Tv[3];
         for (int d = 0; d < 3; d++) {
             double fv = -(F[d].s + F[d].c);
@@ -585,20 +580,20 @@ __device__ __forceinline__ void force_one(const ForceArgs &a, int p) {
     }
 }
 
-// Force, torque and integration of every particle (one workgroup each), or
-// of the particles of group G.g (workgroups walk the group's list).
-template <int D, bool R32, int NT>
-__global__ __launch_bounds__(NT) void k_force(ForceArgs a) {
+// Force, torque and integration of every particle (64 / LPP particles per
+// wavefront, one wavefront per workgroup), or of the particles of group G.g
+// (one particle per wavefront; workgroups walk the group's list).
+template <int D, bool R32, int LPP>
+__global__ __launch_bounds__(64) void k_force(ForceArgs a) {
+    const int lane = (int)threadIdx.x;
     if (a.G.g < 0) {
-        force_one<D, R32, NT>(a, (int)blockIdx.x);
+        const int p = (int)blockIdx.x * (64 / LPP) + lane / LPP;
+        force_lanes<D, R32, LPP>(a, p, lane % LPP, p < a.P.np);
         return;
     }
     const int n = a.G.count[a.G.g];
     const int *lst = a.G.list + (int64_t)a.G.g * a.G.stride;
-    for (int i = (int)blockIdx.x; i < n; i += (int)gridDim.x) {
-        force_one<D, R32, NT>(a, lst[i]);
-        __syncthreads();  // the shared partial sums are reused by the next particle
-    }
+    for (int i = (int)blockIdx.x; i < n; i += (int)gridDim.x) force_lanes<D, R32, 64>(a, lst[i], lane, true);
 }
 
 // Files every particle in its group of the current positions.
@@ -1018,16 +1013,41 @@ hipError_t launch_foot_paint(const FootArgs &a, int D, hipStream_t s) {
     return D == 2 ? paint_s<2, FOOT_NT2, false>(a, s) : paint_s<3, FOOT_NT3, false>(a, s);
 }
 
+// Lanes per particle of the force kernel on the plain step (compile-time
+// knobs for measurement); the slab pipeline's groups take one wavefront per
+// particle.  Measured on MI355X (same bits in every shape): a disc's ~100
+// list entries take 16 lanes, four discs per wavefront (1 166 400 discs:
+// 1.18 against 1.62 ms with a wavefront each, C2: 30 against 37 us); a
+// sphere's ~270 entries keep a whole wavefront (16 or 32 lanes: within 3 %).
+#ifndef FORCE_LPP2
+#define FORCE_LPP2 16
+#endif
+#ifndef FORCE_LPP3
+#define FORCE_LPP3 64
+#endif
+
 hipError_t launch_force(const ForceArgs &a, hipStream_t s) {
     if (a.P.np == 0) return hipSuccess;
-    // one wavefront per particle
-    const dim3 g((unsigned)(a.G.g < 0 ? a.P.np : std::min(a.P.np, GROUP_GRID))), b(64);
+    const dim3 b(64);
+    if (a.G.g >= 0) {
+        const dim3 g((unsigned)std::min(a.P.np, GROUP_GRID));
+        if (a.D == 2) {
+            if (a.rec32) hipLaunchKernelGGL((k_force<2, true, 64>), g, b, 0, s, a);
+            else hipLaunchKernelGGL((k_force<2, false, 64>), g, b, 0, s, a);
+        } else {
+            if (a.rec32) hipLaunchKernelGGL((k_force<3, true, 64>), g, b, 0, s, a);
+            else hipLaunchKernelGGL((k_force<3, false, 64>), g, b, 0, s, a);
+        }
+        return hipGetLastError();
+    }
     if (a.D == 2) {
-        if (a.rec32) hipLaunchKernelGGL((k_force<2, true, 64>), g, b, 0, s, a);
-        else hipLaunchKernelGGL((k_force<2, false, 64>), g, b, 0, s, a);
+        const dim3 g(blocks_for(a.P.np, 64 / FORCE_LPP2));
+        if (a.rec32) hipLaunchKernelGGL((k_force<2, true, FORCE_LPP2>), g, b, 0, s, a);
+        else hipLaunchKernelGGL((k_force<2, false, FORCE_LPP2>), g, b, 0, s, a);
     } else {
-        if (a.rec32) hipLaunchKernelGGL((k_force<3, true, 64>), g, b, 0, s, a);
-        else hipLaunchKernelGGL((k_force<3, false, 64>), g, b, 0, s, a);
+        const dim3 g(blocks_for(a.P.np, 64 / FORCE_LPP3));
+        if (a.rec32) hipLaunchKernelGGL((k_force<3, true, FORCE_LPP3>), g, b, 0, s, a);
+        else hipLaunchKernelGGL((k_force<3, false, FORCE_LPP3>), g, b, 0, s, a);
     }
     return hipGetLastError();
 }

@@ -386,6 +386,37 @@ def test_slot_overflow_is_reported(gpu_lib):
     assert ei.value.code == -5
 
 
+@pytest.mark.parametrize("n_far", [0, 16384])
+def test_contact_overflow_is_reported(gpu_lib, n_far):
+    """A disc of radius 12 ringed by 36 discs of radius 1, each overlapping it
+    by 0.3 (and not each other): 36 contacts, more than the library keeps.
+    Without other discs the contacts run one wavefront per disc; 16 384 more
+    discs far away (a grid of pitch 6.5, so no DEM cell of edge >= 24 holds
+    more than 16) switch them to one thread per disc.  Both report the
+    overflow, and nothing else overflows first (at most two owners per node,
+    at most ten discs per cell around the ring)."""
+    L = 1024
+    R, r, ring = 12.0, 1.0, 12.7
+    c = np.array([928.0, 928.0])
+    ang = 2 * np.pi * np.arange(36) / 36
+    small = c + ring * np.stack([np.cos(ang), np.sin(ang)], axis=1)
+    assert 2 * np.pi * ring / 36 > 2 * r  # ring discs do not touch each other
+    k = int(np.sqrt(n_far))
+    g = (np.arange(k) * 6.5 + 3.0) if k else np.zeros(0)
+    far = np.stack(np.meshgrid(g, g, indexing="ij"), axis=-1).reshape(-1, 2)
+    assert far.shape[0] == n_far and (n_far == 0 or far.max() + 1.0 < c[0] - ring - 2.0)
+    pos2 = np.concatenate([c[None, :], small, far])
+    n = len(pos2)
+    pos = np.concatenate([pos2, np.zeros((n, 1))], axis=1)
+    rad = np.concatenate([[R], np.full(36, r), np.full(n_far, r)])
+    say("contact overflow", n, "discs")
+    s = gpu_lib.Simulation(2, (L, L), 0.8, samples=4, kn=10.0, max_particles=n, max_radius=R)
+    s.set_particles(pos, radius=rad, rho_s=np.full(n, 2.0))
+    with pytest.raises(gpu_lib.LbmError) as ei:
+        s.step(1)
+    assert ei.value.code == -9
+
+
 def test_runaway_particle_is_reported(gpu_lib):
     """A particle that moves more than a box length in one step leaves the
     box after the single periodic wrap of the integrator: the next footprint
