@@ -6,7 +6,7 @@ resolved drag as fallback outside the training envelope.
     python -m paper_1011_2613_amd.closure_pipeline --ensembles 4 --boxes 512 \
         --heldout 64 --out closure.json
 
-Training ensembles use box seeds 1000 + e (e = 0 .. ensembles-1), the
+Training ensembles use box seeds 1000 + e (e = first .. first + ensembles - 1), the
 held-out boxes seed 9000, so no held-out box is seen in training.  Every
 lattice step, force sum and network evaluation runs in the HIP library.
 """
@@ -97,6 +97,8 @@ def cached_ensemble(seed, n_boxes, dirs, save_dir, budget_end=None, **kw):
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--ensembles", type=int, default=2)
+    ap.add_argument("--first-ensemble", type=int, default=0,
+                    help="index of the first training ensemble (box seeds 1000 + index)")
     ap.add_argument("--boxes", type=int, default=512)
     ap.add_argument("--heldout", type=int, default=64)
     ap.add_argument("--max-steps", type=int, default=20000)
@@ -128,7 +130,7 @@ def main(argv=None):
     dirs = [d for d in args.data_dirs.split(",") if d] + ([args.save_dir] if args.save_dir else [])
     run_kw = dict(max_steps=args.max_steps, check_every=args.check_every, tol=args.tol, tune_cache=args.tune_cache)
     Xs, ys, ens_stats, raws = [], [], [], []
-    for e in range(args.ensembles):
+    for e in range(args.first_ensemble, args.first_ensemble + args.ensembles):
         if args.save_raw:
             boxes = E.sample_boxes(args.boxes, 1000 + e)
             X, y, _, rs, st = run_ensemble(boxes, **run_kw)
