@@ -76,3 +76,31 @@ def test_bench_traffic_lookup_by_shape(tmp_path, monkeypatch):
     assert bench.measured_traffic("fp16s", "C3", "64") is None
     monkeypatch.setattr(bench, "kernel_source_sha", lambda: "s2")
     assert bench.measured_traffic("fp32s", "C3", "64") is None
+
+
+def test_closure_ensemble_cache(tmp_path):
+    """Ensembles saved per seed are read back instead of being run again (from
+    the first folder that holds them), and with the time budget spent and no
+    saved copy nothing runs."""
+    import json
+    from paper_1011_2613_amd import closure_pipeline as CP
+    kw = dict(max_steps=20000, tol=1e-5)
+    name = CP._cache_name(1007, 512, 20000, 1e-5)
+    X = np.arange(12, dtype=np.float32).reshape(3, 4)
+    y = np.array([1.0, 2.0, 3.0])
+    box_of = np.array([0, 0, 1])
+    rs = np.array([True, False, True])
+    st = {"boxes": 512, "steady_boxes": 1, "samples": 2, "run_s": 1.5, "mlups": 3.0e4}
+    other = tmp_path / "other"
+    other.mkdir()
+    np.savez_compressed(str(tmp_path / name), X=X, y=y, box_of=box_of, row_steady=rs, stats=json.dumps(st))
+    got = CP.cached_ensemble(1007, 512, [str(other), str(tmp_path)], None, budget_end=0.0, **kw)
+    assert got is not None
+    gX, gy, gb, grs, gst = got
+    assert np.array_equal(gX, X) and np.array_equal(gy, y) and np.array_equal(gb, box_of)
+    assert np.array_equal(grs, rs)
+    assert gst["cached"] is True and gst["samples"] == 2 and gst["run_s"] == 1.5
+    # another seed, budget spent: nothing is run
+    assert CP.cached_ensemble(1008, 512, [str(tmp_path)], None, budget_end=0.0, **kw) is None
+    # the file name carries the box count, the step cap and the tolerance
+    assert CP._cache_name(1007, 64, 20000, 1e-5) != name and CP._cache_name(1007, 512, 10000, 1e-5) != name
