@@ -358,14 +358,15 @@ __device__ __forceinline__ void lane_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Footprints of discs, 64 / LPP discs per wavefront (one wavefront per
-// workgroup, LPP lanes per disc): the phases of foot_one for each disc in its
-// own lanes and LDS buffers, prefix sums over the disc's lanes, and runs of
-// owner-count words kept inside a disc's lanes (two discs may cover one
-// node).  Each disc's list, owner claims and counts are those foot_one gives.
-template <int S, int LPP>
+// Footprints of 64 / LPP particles per wavefront (one wavefront per
+// workgroup, LPP lanes per particle): the phases of foot_one for each
+// particle in its own lanes and LDS buffers, prefix sums over the particle's
+// lanes, and runs of owner-count words kept inside a particle's lanes (two
+// particles may cover one node).  Each particle's list, owner claims and
+// counts are those foot_one gives.
+template <int D, int S, int LPP>
 __global__ __launch_bounds__(64) void k_foot_sub(FootArgs a) {
-    constexpr int D = 2, G = 64 / LPP, CHUNK = 512;
+    constexpr int G = 64 / LPP, CHUNK = D == 3 ? 1024 : 512;
     __shared__ uint16_t s_cnt[G][CHUNK];
     __shared__ uint16_t s_todo[G][CHUNK];
     __shared__ int s_ntodo[G];
@@ -384,23 +385,27 @@ __global__ __launch_bounds__(64) void k_foot_sub(FootArgs a) {
     bool placed = live;
     for (int d = 0; d < D; d++) {
         const double c = a.P.x[d * P + q];
-        const double L = d == 0 ? a.g.Lx : a.g.Ly;
+        const double L = d == 0 ? a.g.Lx : (d == 1 ? a.g.Ly : a.g.Lz);
         placed = placed && ((d == 1 && a.g.wall_y) ? (c > -L && c < 2.0 * L) : (c >= 0.0 && c < L));
     }
     if (live && !placed && sub == 0) atomicOr(a.flags, FLAG_NONFINITE);
     const int ext0 = hi[0] - lo[0] + 1, ext1 = hi[1] - lo[1] + 1;
-    const int items = placed ? ext0 * ext1 : 0;
+    const int ext2 = D == 3 ? hi[2] - lo[2] + 1 : 1;
+    const int items = placed ? ext0 * ext1 * ext2 : 0;
     const double R2 = a.P.R[q] * a.P.R[q];
-    const double xp0 = a.P.x[q], xp1 = a.P.x[P + q];
+    const double xp0 = a.P.x[q], xp1 = a.P.x[P + q], xp2 = D == 3 ? a.P.x[2 * P + q] : 0.0;
     const int64_t N = a.g.N;
     const int cap = a.P.list_cap;
     uint32_t *list = a.P.list + (int64_t)q * cap;
-    const float inv0 = 1.0f / (float)ext0;
-    auto node_of = [&](int item, int &kx, int &ky, int &ix, int &iy) {
-        ky = div_small(item, ext0, inv0);
-        kx = item - ky * ext0;
+    const float inv0 = 1.0f / (float)ext0, inv1 = 1.0f / (float)ext1;
+    auto node_of = [&](int item, int &kx, int &ky, int &kz, int &ix, int &iy, int &iz) {
+        const int rest = div_small(item, ext0, inv0);
+        kx = item - rest * ext0;
+        kz = D == 3 ? div_small(rest, ext1, inv1) : 0;
+        ky = rest - kz * ext1;
         iy = wrap1(a.g, 1, lo[1] + ky);
         ix = wrap1(a.g, 0, lo[0] + kx);
+        iz = D == 3 ? wrap1(a.g, 2, lo[2] + kz) : 0;
     };
     int base = 0;
     for (int c0 = 0; __any(c0 < items); c0 += CHUNK) {
@@ -410,10 +415,12 @@ __global__ __launch_bounds__(64) void k_foot_sub(FootArgs a) {
         // (A) classify
 #pragma unroll 1
         for (int i = sub; i < nc; i += LPP) {
-            int kx, ky, ix, iy;
-            node_of(c0 + i, kx, ky, ix, iy);
+            int kx, ky, kz, ix, iy, iz;
+            node_of(c0 + i, kx, ky, kz, ix, iy, iz);
             int cls = 0;
-            if (iy >= 0) cls = classify<D, S>(ndisp(a.g, 0, ix, xp0), ndisp(a.g, 1, iy, xp1), 0.0, R2);
+            if (iy >= 0)
+                cls = classify<D, S>(ndisp(a.g, 0, ix, xp0), ndisp(a.g, 1, iy, xp1),
+                                     D == 3 ? ndisp(a.g, 2, iz, xp2) : 0.0, R2);
             if (cls < 0) s_todo[grp][atomicAdd(&s_ntodo[grp], 1)] = (uint16_t)i;
             else s_cnt[grp][i] = (uint16_t)cls;
         }
@@ -423,9 +430,10 @@ __global__ __launch_bounds__(64) void k_foot_sub(FootArgs a) {
 #pragma unroll 1
         for (int j = sub; j < ntodo; j += LPP) {
             const int i = s_todo[grp][j];
-            int kx, ky, ix, iy;
-            node_of(c0 + i, kx, ky, ix, iy);
-            s_cnt[grp][i] = (uint16_t)sample_count<D, S>(ndisp(a.g, 0, ix, xp0), ndisp(a.g, 1, iy, xp1), 0.0, R2);
+            int kx, ky, kz, ix, iy, iz;
+            node_of(c0 + i, kx, ky, kz, ix, iy, iz);
+            s_cnt[grp][i] = (uint16_t)sample_count<D, S>(ndisp(a.g, 0, ix, xp0), ndisp(a.g, 1, iy, xp1),
+                                                         D == 3 ? ndisp(a.g, 2, iz, xp2) : 0.0, R2);
         }
         lane_sync();
         // (C1) covered nodes in node order into s_todo: each lane takes
@@ -450,15 +458,15 @@ __global__ __launch_bounds__(64) void k_foot_sub(FootArgs a) {
 #pragma unroll 1
         for (int k0 = 0; __any(k0 < ncov); k0 += LPP) {
             const int k = k0 + sub;
-            int count = 0, kx = 0, ky = 0;
+            int count = 0, kx = 0, ky = 0, kz = 0;
             int64_t n = 0;
             long long key = -1;
             if (k < ncov) {
                 const int i = s_todo[grp][k];
                 count = s_cnt[grp][i];
-                int ix, iy;
-                node_of(c0 + i, kx, ky, ix, iy);
-                n = (int64_t)ix + (int64_t)a.g.nx * (int64_t)iy;
+                int ix, iy, iz;
+                node_of(c0 + i, kx, ky, kz, ix, iy, iz);
+                n = (int64_t)ix + (int64_t)a.g.nx * ((int64_t)iy + (int64_t)a.g.ny * iz);
                 key = (long long)(n >> 3);
             }
             const int byte = (int)(n & 7);
@@ -494,7 +502,7 @@ __global__ __launch_bounds__(64) void k_foot_sub(FootArgs a) {
                     a.slots[(int64_t)slot * N + n] = ((uint32_t)p << SLOT_COUNT_BITS) | (uint32_t)count;
                 else
                     atomicOr(a.flags, FLAG_SLOT_OVERFLOW);
-                if (base + k < cap) list[base + k] = list_entry(count, kx, ky, 0);
+                if (base + k < cap) list[base + k] = list_entry(count, kx, ky, kz);
             }
         }
         base += ncov;
@@ -1165,23 +1173,29 @@ static hipError_t paint_s(const FootArgs &a, hipStream_t s) {
 // discs per wavefront (k_foot_sub, 78 registers, six wavefronts per SIMD).
 // Measured on MI355X (same bits in every shape): 1 166 400 discs 1.96
 // against 2.75 ms with a wavefront per disc (32 lanes: 1.72 ms, but the step
-// was slower), C2 47.6 against 52.7 us.  64 keeps foot_one.
+// was slower), C2 47.6 against 52.7 us.
 #ifndef FOOT_LPP2
 #define FOOT_LPP2 16
 #endif
+// Spheres: one wavefront per sphere in k_foot_sub (8 317 spheres: 81 against
+// 83 us for foot_one's two wavefronts, 85 us for two spheres per wavefront);
+// a value above 64 keeps foot_one.
+#ifndef FOOT_LPP3
+#define FOOT_LPP3 64
+#endif
 
-template <int LPP>
+template <int D, int LPP>
 static hipError_t paint_sub(const FootArgs &a, hipStream_t s) {
     const dim3 g(blocks_for(a.P.np, 64 / LPP)), b(64);
     switch (a.S) {
-        case 1: hipLaunchKernelGGL((k_foot_sub<1, LPP>), g, b, 0, s, a); break;
-        case 2: hipLaunchKernelGGL((k_foot_sub<2, LPP>), g, b, 0, s, a); break;
-        case 3: hipLaunchKernelGGL((k_foot_sub<3, LPP>), g, b, 0, s, a); break;
-        case 4: hipLaunchKernelGGL((k_foot_sub<4, LPP>), g, b, 0, s, a); break;
-        case 5: hipLaunchKernelGGL((k_foot_sub<5, LPP>), g, b, 0, s, a); break;
-        case 6: hipLaunchKernelGGL((k_foot_sub<6, LPP>), g, b, 0, s, a); break;
-        case 7: hipLaunchKernelGGL((k_foot_sub<7, LPP>), g, b, 0, s, a); break;
-        default: hipLaunchKernelGGL((k_foot_sub<8, LPP>), g, b, 0, s, a); break;
+        case 1: hipLaunchKernelGGL((k_foot_sub<D, 1, LPP>), g, b, 0, s, a); break;
+        case 2: hipLaunchKernelGGL((k_foot_sub<D, 2, LPP>), g, b, 0, s, a); break;
+        case 3: hipLaunchKernelGGL((k_foot_sub<D, 3, LPP>), g, b, 0, s, a); break;
+        case 4: hipLaunchKernelGGL((k_foot_sub<D, 4, LPP>), g, b, 0, s, a); break;
+        case 5: hipLaunchKernelGGL((k_foot_sub<D, 5, LPP>), g, b, 0, s, a); break;
+        case 6: hipLaunchKernelGGL((k_foot_sub<D, 6, LPP>), g, b, 0, s, a); break;
+        case 7: hipLaunchKernelGGL((k_foot_sub<D, 7, LPP>), g, b, 0, s, a); break;
+        default: hipLaunchKernelGGL((k_foot_sub<D, 8, LPP>), g, b, 0, s, a); break;
     }
     return hipGetLastError();
 }
@@ -1191,7 +1205,8 @@ hipError_t launch_foot_paint(const FootArgs &a, int D, hipStream_t s) {
     // the table lookup is a kernel of its own, so the sampling kernel keeps
     // its registers
     if (a.tab) return D == 2 ? paint_s<2, FOOT_NT2, true>(a, s) : paint_s<3, FOOT_NT3, true>(a, s);
-    if (D == 2 && FOOT_LPP2 < 64 && a.G.g < 0) return paint_sub<FOOT_LPP2 < 64 ? FOOT_LPP2 : 32>(a, s);
+    if (D == 2 && FOOT_LPP2 <= 64 && a.G.g < 0) return paint_sub<2, FOOT_LPP2 <= 64 ? FOOT_LPP2 : 64>(a, s);
+    if (D == 3 && FOOT_LPP3 <= 64 && a.G.g < 0) return paint_sub<3, FOOT_LPP3 <= 64 ? FOOT_LPP3 : 64>(a, s);
     return D == 2 ? paint_s<2, FOOT_NT2, false>(a, s) : paint_s<3, FOOT_NT3, false>(a, s);
 }
 
